@@ -97,7 +97,8 @@ def problem_digest(pr: codes.Problem) -> str:
 def _cache_dir() -> str:
     d = os.environ.get("BSD_INPUT_CACHE")
     if not d:
-        d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out", "input_cache")
+        import tempfile
+        d = os.path.join(tempfile.gettempdir(), "bsd_input_cache")
     return d
 
 

@@ -1,0 +1,162 @@
+/*
+ * bsd.h -- C ABI of the MI355X beam-search decoder for quantum LDPC codes.
+ *
+ * The decoder is the BP-guided beam search of "Beam search decoder for
+ * quantum LDPC codes" (Ye, Wecker, Delfosse): min-sum belief propagation on
+ * the Tanner graph of a check matrix H (Appendix A, eqs. (1)-(4)), masked BP
+ * runs that fix the least reliable error node to 0 and to 1 (Algorithm 2),
+ * and a beam of paths scored by their summed posterior LLRs and pruned to
+ * beam_width (Algorithm 3, Appendix B).  All decoding runs on the GPU in
+ * hand-written HIP kernels for gfx950.
+ *
+ * Conventions
+ *  - Matrices are given in compressed sparse column form (CSC): colptr has
+ *    n+1 entries starting at 0, rowidx lists the rows of column j in
+ *    colptr[j]..colptr[j+1]-1 in strictly ascending order.
+ *  - Edge messages exchanged through bsd_bp_run are indexed by the position
+ *    of the edge in the CSC of H.
+ *  - All functions return a bsd_status; on failure bsd_last_error() returns
+ *    a message for the calling thread.  Outputs are unspecified on failure.
+ *  - A syndrome that no correction satisfies is not an error: the shot is
+ *    reported with converged = 0.
+ */
+#ifndef BSD_H
+#define BSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BSD_OK = 0,
+  BSD_EINVAL = -1,  /* invalid argument (message says which) */
+  BSD_ENOMEM = -2,  /* device or host allocation failed */
+  BSD_EDEVICE = -3, /* HIP runtime error (message includes hipGetErrorString) */
+  BSD_EBUSY = -4    /* code handle still in use */
+} bsd_status;
+
+typedef enum {
+  BSD_MODE_BATCHED = 0, /* one persistent kernel decodes every shot of the call */
+  BSD_MODE_PLAIN = 1    /* one kernel launch per BP run; beam bookkeeping on the host */
+} bsd_mode;
+
+/* Opaque handle: the device-resident Tanner graph of H, the prior LLRs and
+ * the logical matrix A. */
+typedef struct bsd_code_s* bsd_code;
+
+/* Decoder parameters: the five parameters of Algorithm 3 (Table I names
+ * configurations by them) plus the min-sum scaling and the execution mode.
+ *   max_rounds       rounds of branching after the initial BP run (>= 0)
+ *   beam_width       paths kept after each round (1..64)
+ *   initial_iters    iterations of the initial BP run (>= 0)
+ *   iters_per_round  iterations of each masked BP run (>= 0)
+ *   num_results      solutions to collect before returning (1..64); with
+ *                    more than one, the lightest by wt(e) = sum_j e_j
+ *                    log((1-p_j)/p_j) is returned (Appendix B)
+ *   alpha            scaling of the detector-to-error messages of eq. (1);
+ *                    1.0 is eq. (1) as printed (> 0, finite)
+ *   mode             a bsd_mode value */
+typedef struct {
+  int32_t max_rounds;
+  int32_t beam_width;
+  int32_t initial_iters;
+  int32_t iters_per_round;
+  int32_t num_results;
+  float alpha;
+  int32_t mode;
+} bsd_params;
+
+/* Work counters of one bsd_decode_ex call. */
+typedef struct {
+  int64_t runs;         /* BP runs executed (initial and masked) */
+  int64_t iterations;   /* BP iterations summed over runs */
+  int64_t edge_updates; /* iterations x Tanner edges, summed over runs */
+  int64_t deep_shots;   /* shots whose initial BP run did not converge */
+  double kernel_ms;     /* device time of the decoding kernels (HIP events) */
+} bsd_stats;
+
+/* Build a code handle on the current HIP device (Appendix A: the decoding
+ * problem (H, A, p)).
+ *   m, n, k      detectors (rows of H), fault columns, logical rows of A
+ *   h_colptr     host, n+1 int32: CSC column pointers of H
+ *   h_rowidx     host, nnz int32: CSC row indices of H (ascending per column)
+ *   p            host, n doubles: fault probabilities, 0 < p_j < 1; the
+ *                prior LLRs log((1-p_j)/p_j) are formed in double precision
+ *                and rounded once to float
+ *   l_colptr     host, n+1 int32: CSC column pointers of A (may be NULL if k = 0)
+ *   l_rowidx     host, int32: CSC row indices of A
+ *   out          receives the handle
+ * The caller keeps ownership of every array; they may be freed on return.
+ * Limits: m < 65536, k <= 64, column degree <= 8, row degree <= 255, and
+ * the fp32 edge messages of one BP run (4 * nnz bytes) must fit in the
+ * 160 KB LDS of one compute unit (nnz <= 39936).
+ * Errors: BSD_EINVAL for malformed CSC, p outside (0,1) or limits exceeded;
+ * BSD_ENOMEM, BSD_EDEVICE. */
+bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_colptr,
+                           const int32_t* h_rowidx, const double* p, const int32_t* l_colptr,
+                           const int32_t* l_rowidx, bsd_code* out);
+
+/* Release a code handle and every device buffer it owns.  BSD_EBUSY if a
+ * decode on it is still running. */
+bsd_status bsd_code_destroy(bsd_code code);
+
+/* Decode `shots` syndromes with the beam search of Algorithm 3.
+ *   syndromes      device, uint8 [shots x m], values 0/1 (s = H e)
+ *   corrections    device, uint8 [shots x n]: the returned e-hat (0/1)
+ *   logical_flips  device, uint8 [shots x k]: A e-hat mod 2 (compare with A e)
+ *   converged      device, uint8 [shots]: 1 iff H e-hat = s was reached
+ *   stream         hipStream_t to run on (NULL: the default stream)
+ * Buffers are owned by the caller and must not overlap.  The call returns
+ * after the work on `stream` has completed (it reads back a status word).
+ * Errors: BSD_EINVAL for bad parameters or syndrome bytes outside {0,1};
+ * BSD_ENOMEM when the workspace cannot be allocated; BSD_EDEVICE. */
+bsd_status bsd_decode(bsd_code code, const bsd_params* prm, int64_t shots,
+                      const uint8_t* syndromes, uint8_t* corrections, uint8_t* logical_flips,
+                      uint8_t* converged, void* stream);
+
+/* As bsd_decode, also filling `stats` (host, may be NULL) and, when
+ * `latency_ticks` (device, uint32 [shots], may be NULL) is given, the
+ * per-shot decode time in ticks of the 100 MHz device clock (from the start
+ * of the shot's initial BP run to the write of its result). */
+bsd_status bsd_decode_ex(bsd_code code, const bsd_params* prm, int64_t shots,
+                         const uint8_t* syndromes, uint8_t* corrections, uint8_t* logical_flips,
+                         uint8_t* converged, void* stream, bsd_stats* stats,
+                         uint32_t* latency_ticks);
+
+/* One run of masked BP (Algorithm 2) on the GPU, for checking messages.
+ *   e_start    device, float [nnz] in CSC edge order: E(0); NULL = priors
+ *   pairs      host, int32 [2 * npairs]: (column, value) of the masked nodes
+ *   syndrome   device, uint8 [m]
+ *   max_iters  iterations to run (>= 0); stop_on_converge != 0 stops at the
+ *              first iteration whose hard decision satisfies H e = s'
+ *   alpha      scaling of eq. (1)
+ * Outputs (device, may be NULL): e_out float [nnz] (E at the last iteration,
+ * CSC order), sum_llr float [n] (posteriors summed over the iterations run;
+ * 0 on masked nodes), ehat uint8 [n] (last hard decision; masked nodes hold
+ * their value if the run converged, else 0), and on the host: iters,
+ * converged, next_pos (least reliable unmasked node, -1 if none) and score
+ * (sum of |sum_llr| over unmasked nodes divided by iters).
+ * Synchronous.  Errors: BSD_EINVAL, BSD_EDEVICE. */
+bsd_status bsd_bp_run(bsd_code code, const float* e_start, const int32_t* pairs, int32_t npairs,
+                      const uint8_t* syndrome, int32_t max_iters, float alpha,
+                      int32_t stop_on_converge, float* e_out, float* sum_llr, uint8_t* ehat,
+                      int32_t* iters, int32_t* converged, int32_t* next_pos, float* score,
+                      void* stream);
+
+/* Geometry of a code handle: nnz of H and the threads per workgroup and
+ * workgroups the batched kernel will use.  Any pointer may be NULL. */
+bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, int32_t* grid_blocks,
+                         int32_t* lds_bytes);
+
+/* Thread-local message describing the last failure in this thread. */
+const char* bsd_last_error(void);
+
+/* Library version string. */
+const char* bsd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSD_H */

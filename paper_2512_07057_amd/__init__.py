@@ -1,0 +1,208 @@
+"""Python binding of the MI355X beam-search decoder (libbsd.so).
+
+Argument marshalling only: every step of decoding runs in the HIP kernels
+behind the C ABI declared in include/bsd.h.  PyTorch supplies device memory
+and streams.  The library must have been built (``build.build()``); there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsd.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "bsd.h")
+
+BSD_OK, BSD_EINVAL, BSD_ENOMEM, BSD_EDEVICE, BSD_EBUSY = 0, -1, -2, -3, -4
+MODE_BATCHED, MODE_PLAIN = 0, 1
+_lib = None
+
+
+class BsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bsd status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("max_rounds", C.c_int32), ("beam_width", C.c_int32),
+                ("initial_iters", C.c_int32), ("iters_per_round", C.c_int32),
+                ("num_results", C.c_int32), ("alpha", C.c_float), ("mode", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("runs", C.c_int64), ("iterations", C.c_int64), ("edge_updates", C.c_int64),
+                ("deep_shots", C.c_int64), ("kernel_ms", C.c_double)]
+
+
+def exported_symbols_from_header(path: str = HEADER) -> list[str]:
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(bsd_[a-z_]+)\s*\(", text)))
+
+
+def load():
+    """Load libbsd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2512_07057_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    i32p = C.POINTER(C.c_int32)
+    lib.bsd_last_error.restype = C.c_char_p
+    lib.bsd_version.restype = C.c_char_p
+    lib.bsd_code_create.restype = C.c_int
+    lib.bsd_code_create.argtypes = [i32, i32, i32, i32p, i32p, C.POINTER(C.c_double), i32p, i32p,
+                                    C.POINTER(P)]
+    lib.bsd_code_destroy.restype = C.c_int
+    lib.bsd_code_destroy.argtypes = [P]
+    lib.bsd_code_info.restype = C.c_int
+    lib.bsd_code_info.argtypes = [P, C.POINTER(i64), i32p, i32p, i32p]
+    lib.bsd_decode.restype = C.c_int
+    lib.bsd_decode.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P]
+    lib.bsd_decode_ex.restype = C.c_int
+    lib.bsd_decode_ex.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P, C.POINTER(Stats), P]
+    lib.bsd_bp_run.restype = C.c_int
+    lib.bsd_bp_run.argtypes = [P, P, i32p, i32, P, i32, C.c_float, i32, P, P, P, i32p, i32p, i32p,
+                               C.POINTER(C.c_float), P]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != BSD_OK:
+        raise BsdError(rc, load().bsd_last_error().decode())
+
+
+def version() -> str:
+    return load().bsd_version().decode()
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_params(max_rounds, beam_width, initial_iters, iters_per_round, num_results=1,
+                alpha=0.625, mode=MODE_BATCHED) -> Params:
+    return Params(int(max_rounds), int(beam_width), int(initial_iters), int(iters_per_round),
+                  int(num_results), float(alpha), int(mode))
+
+
+class Code:
+    """A decoding problem (H, A, p) resident on the current HIP device."""
+
+    def __init__(self, m, n, colptr, rowidx, p, L=None):
+        self._lib = load()
+        self.m, self.n = int(m), int(n)
+        colptr, rowidx = _i32(colptr), _i32(rowidx)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        if L is None:
+            L = np.zeros((0, self.n), np.uint8)
+        L = np.asarray(L, dtype=np.uint8)
+        self.k = int(L.shape[0])
+        cols = [np.nonzero(L[:, j])[0] for j in range(self.n)]
+        lptr = np.zeros(self.n + 1, np.int32)
+        lptr[1:] = np.cumsum([len(c) for c in cols])
+        lidx = np.concatenate(cols).astype(np.int32) if lptr[-1] else np.zeros(1, np.int32)
+        h = C.c_void_p()
+        i32p = C.POINTER(C.c_int32)
+        rc = self._lib.bsd_code_create(
+            self.m, self.n, self.k, colptr.ctypes.data_as(i32p), rowidx.ctypes.data_as(i32p),
+            p.ctypes.data_as(C.POINTER(C.c_double)), lptr.ctypes.data_as(i32p),
+            lidx.ctypes.data_as(i32p), C.byref(h))
+        _check(rc)
+        self._h = h
+        self.nnz = int(colptr[-1])
+
+    @classmethod
+    def from_problem(cls, pr):
+        return cls(pr.m, pr.n, pr.colptr, pr.rowidx, pr.p, pr.L)
+
+    def info(self) -> dict:
+        nnz, blk, grid, lds = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self._lib.bsd_code_info(self._h, C.byref(nnz), C.byref(blk), C.byref(grid), C.byref(lds)))
+        return {"nnz": nnz.value, "block": blk.value, "grid": grid.value, "lds_bytes": lds.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.bsd_code_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def decode(self, syndromes, params: Params, stream=None, latency=False, out=None):
+        """Decode a [shots, m] uint8 CUDA tensor; returns a dict of tensors and stats."""
+        import torch
+        syn = syndromes
+        if syn.dtype != torch.uint8 or not syn.is_cuda or not syn.is_contiguous():
+            raise ValueError("syndromes must be a contiguous uint8 CUDA tensor")
+        shots = syn.shape[0] if syn.dim() == 2 else 0
+        if syn.dim() != 2 or syn.shape[1] != self.m:
+            raise ValueError(f"syndromes must have shape [shots, {self.m}]")
+        dev = syn.device
+        if out is None:
+            out = {
+                "corrections": torch.empty((shots, self.n), dtype=torch.uint8, device=dev),
+                "flips": torch.empty((shots, max(self.k, 1)), dtype=torch.uint8, device=dev),
+                "converged": torch.empty((shots,), dtype=torch.uint8, device=dev),
+            }
+        lat = torch.empty((shots,), dtype=torch.int32, device=dev) if latency else None
+        st = Stats()
+        rc = self._lib.bsd_decode_ex(self._h, C.byref(params), shots, _ptr(syn),
+                                     _ptr(out["corrections"]), _ptr(out["flips"]),
+                                     _ptr(out["converged"]), _stream(stream), C.byref(st),
+                                     _ptr(lat))
+        _check(rc)
+        res = dict(out)
+        if self.k == 0:
+            res["flips"] = res["flips"][:, :0]
+        res["stats"] = {f: getattr(st, f) for f, _ in Stats._fields_}
+        if latency:
+            res["latency_ticks"] = lat
+        return res
+
+    def bp_run(self, syndrome, max_iters, alpha=0.625, e_start=None, pairs=(), stop=True,
+               stream=None):
+        """One masked BP run (Algorithm 2) on the GPU; messages in CSC edge order."""
+        import torch
+        if syndrome.dtype != torch.uint8 or not syndrome.is_cuda or syndrome.numel() != self.m:
+            raise ValueError("syndrome must be a uint8 CUDA tensor with m entries")
+        dev = syndrome.device
+        if e_start is not None:
+            if e_start.dtype != torch.float32 or not e_start.is_cuda or e_start.numel() != self.nnz:
+                raise ValueError("e_start must be a float32 CUDA tensor with nnz entries")
+            e_start = e_start.contiguous()
+        pairs = list(pairs or [])
+        parr = np.array([[int(c), int(v)] for c, v in pairs], dtype=np.int32).reshape(-1)
+        e_out = torch.empty(self.nnz, dtype=torch.float32, device=dev)
+        sl = torch.empty(self.n, dtype=torch.float32, device=dev)
+        eh = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        it, cv, npos = C.c_int32(), C.c_int32(), C.c_int32()
+        sc = C.c_float()
+        pp = parr.ctypes.data_as(C.POINTER(C.c_int32)) if len(pairs) else None
+        rc = self._lib.bsd_bp_run(self._h, _ptr(e_start), pp, len(pairs), _ptr(syndrome.contiguous()),
+                                  int(max_iters), float(alpha), 1 if stop else 0, _ptr(e_out),
+                                  _ptr(sl), _ptr(eh), C.byref(it), C.byref(cv), C.byref(npos),
+                                  C.byref(sc), _stream(stream))
+        _check(rc)
+        return {"e": e_out, "sum_llr": sl, "ehat": eh, "iters": it.value,
+                "converged": bool(cv.value), "next_pos": npos.value, "score": sc.value}

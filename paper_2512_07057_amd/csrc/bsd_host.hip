@@ -1,0 +1,657 @@
+// Host runtime of the beam-search decoder: the C ABI declared in bsd.h.
+//
+// bsd_code_create renumbers the detector rows by descending degree, lays the
+// edge messages out as jagged diagonals (the order they have in LDS and in
+// every device slot), forms the prior LLRs in double precision, and uploads
+// the graph once.  bsd_decode runs either the persistent batched kernel
+// (every shot of the call in one launch, beams advanced on the device) or
+// the plain form (one launch per BP run, beam bookkeeping on the host).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bsd.h"
+#include "bsd_internal.h"
+
+using namespace bsd;
+
+namespace {
+
+thread_local std::string g_err;
+
+bsd_status fail(bsd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OR_FAIL(expr)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(BSD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));                \
+  } while (0)
+
+template <class T>
+hipError_t dev_upload(T** dst, const std::vector<T>& v) {
+  size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+uint32_t pow2_at_least(uint64_t x) {
+  uint32_t c = 1;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+}  // namespace
+
+struct bsd_code_s {
+  int device = 0;
+  DevGraph g{};
+  int block = 64, cpt = 1, grid = 1;
+  size_t lds = 0;
+  std::vector<void*> owned;  // device buffers of the graph
+  std::vector<int32_t> colptr, rowidx;
+  // Batched workspace (grown on demand).
+  int ws_bw = 0;
+  int nctx = 0;
+  BatchState* st = nullptr;
+  BatchState* st_host = nullptr;  // pinned
+  uint32_t* work_ring = nullptr;
+  uint32_t work_cap = 0;
+  uint32_t* ctx_ring = nullptr;
+  uint32_t ctx_cap = 0;
+  Ctx* ctxs = nullptr;
+  char* slots = nullptr;
+  size_t slot_stride = 0;
+  // Plain-form and single-run workspace.
+  char* pslots = nullptr;
+  int p_bw = 0;
+  int32_t* d_pairs = nullptr;
+  int32_t* d_result = nullptr;
+  uint32_t* d_error = nullptr;
+  int32_t* h_pinned = nullptr;  // pairs staging [kMaxRounds] + result [4] + error [1]
+  std::mutex mu;
+  std::atomic<int> busy{0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+void free_workspace(bsd_code c) {
+  hipFree(c->st);
+  hipHostFree(c->st_host);
+  hipFree(c->work_ring);
+  hipFree(c->ctx_ring);
+  hipFree(c->ctxs);
+  hipFree(c->slots);
+  c->st = nullptr;
+  c->st_host = nullptr;
+  c->work_ring = c->ctx_ring = nullptr;
+  c->ctxs = nullptr;
+  c->slots = nullptr;
+  c->ws_bw = 0;
+}
+
+bsd_status ensure_batched(bsd_code c, int bw) {
+  if (c->ws_bw >= bw && c->st) return BSD_OK;
+  free_workspace(c);
+  const int nctx = c->grid + 64;
+  const int per = 3 * bw + 1;
+  c->slot_stride = slot_bytes(c->g);
+  const size_t slot_total = (size_t)nctx * per * c->slot_stride;
+  c->work_cap = pow2_at_least((uint64_t)nctx * 2 * bw + 1);
+  c->ctx_cap = pow2_at_least((uint64_t)nctx + 1);
+  if (hipMalloc((void**)&c->st, sizeof(BatchState)) != hipSuccess ||
+      hipHostMalloc((void**)&c->st_host, sizeof(BatchState), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&c->work_ring, (size_t)c->work_cap * 4) != hipSuccess ||
+      hipMalloc((void**)&c->ctx_ring, (size_t)c->ctx_cap * 4) != hipSuccess ||
+      hipMalloc((void**)&c->ctxs, (size_t)nctx * sizeof(Ctx)) != hipSuccess ||
+      hipMalloc((void**)&c->slots, slot_total) != hipSuccess) {
+    free_workspace(c);
+    (void)hipGetLastError();
+    return fail(BSD_ENOMEM, "cannot allocate the batched workspace (%zu bytes of slots)", slot_total);
+  }
+  c->nctx = nctx;
+  c->ws_bw = bw;
+  return BSD_OK;
+}
+
+bsd_status ensure_plain(bsd_code c, int bw) {
+  if (!c->d_pairs) {
+    if (hipMalloc((void**)&c->d_pairs, kMaxRounds * 4) != hipSuccess ||
+        hipMalloc((void**)&c->d_result, 16) != hipSuccess ||
+        hipMalloc((void**)&c->d_error, 4) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_pinned, (kMaxRounds + 8) * 4, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot allocate the single-run workspace");
+    }
+  }
+  if (bw > 0 && c->p_bw < bw) {
+    hipFree(c->pslots);
+    c->pslots = nullptr;
+    c->slot_stride = slot_bytes(c->g);
+    if (hipMalloc((void**)&c->pslots, (size_t)(3 * bw + 1) * c->slot_stride) != hipSuccess) {
+      (void)hipGetLastError();
+      c->p_bw = 0;
+      return fail(BSD_ENOMEM, "cannot allocate plain-form slots");
+    }
+    c->p_bw = bw;
+  }
+  return BSD_OK;
+}
+
+bsd_status check_params(const bsd_code c, const bsd_params* p) {
+  if (!p) return fail(BSD_EINVAL, "params is NULL");
+  if (p->max_rounds < 0 || p->max_rounds > kMaxRounds)
+    return fail(BSD_EINVAL, "max_rounds must be in [0, %d]", kMaxRounds);
+  if (p->beam_width < 1 || p->beam_width > kMaxBw)
+    return fail(BSD_EINVAL, "beam_width must be in [1, %d]", kMaxBw);
+  if (p->initial_iters < 0 || p->iters_per_round < 0)
+    return fail(BSD_EINVAL, "iteration counts must be >= 0");
+  if (p->num_results < 1 || p->num_results > kMaxResults)
+    return fail(BSD_EINVAL, "num_results must be in [1, %d]", kMaxResults);
+  if (p->num_results != 1)
+    return fail(BSD_EINVAL, "num_results > 1 is not supported by the GPU path yet");
+  if (!(p->alpha > 0.f) || !std::isfinite(p->alpha))
+    return fail(BSD_EINVAL, "alpha must be positive and finite");
+  if (p->mode != BSD_MODE_BATCHED && p->mode != BSD_MODE_PLAIN)
+    return fail(BSD_EINVAL, "unknown mode %d", p->mode);
+  (void)c;
+  return BSD_OK;
+}
+
+struct RunOut {
+  int iters, conv, next_pos;
+  float score;
+};
+
+// One BP run of the plain form: pairs up, launch, result down (synchronous).
+bsd_status plain_run(bsd_code c, hipStream_t s, const float* parent, const std::vector<int32_t>& pairs,
+                     const uint8_t* syn, int T, float alpha, float* out_msg, uint32_t* out_bits,
+                     RunOut* r) {
+  SingleArgs a{};
+  a.g = c->g;
+  a.parent = parent;
+  a.npairs = (int)pairs.size();
+  if (!pairs.empty()) {
+    std::memcpy(c->h_pinned, pairs.data(), pairs.size() * 4);
+    HIP_OR_FAIL(hipMemcpyAsync(c->d_pairs, c->h_pinned, pairs.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  a.pairs = c->d_pairs;
+  a.syn = syn;
+  a.max_iters = T;
+  a.stop = 1;
+  a.alpha = alpha;
+  a.want_score = 1;
+  a.out_msg = out_msg;
+  a.out_ehat_bits = out_bits;
+  a.result = c->d_result;
+  a.error = c->d_error;
+  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->lds, s));
+  int32_t* res = c->h_pinned + kMaxRounds;
+  HIP_OR_FAIL(hipMemcpyAsync(res, c->d_result, 16, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  r->iters = res[0];
+  r->conv = res[1];
+  r->next_pos = res[2];
+  std::memcpy(&r->score, &res[3], 4);
+  return BSD_OK;
+}
+
+struct HostPath {
+  int slot;
+  std::vector<int32_t> pairs;
+  int next_pos;
+  float score;
+  int gen;
+};
+
+bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                        uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
+                        bsd_stats* stats) {
+  const DevGraph& g = c->g;
+  bsd_status st = ensure_plain(c, p->beam_width);
+  if (st != BSD_OK) return st;
+  HIP_OR_FAIL(hipMemsetAsync(c->d_error, 0, 4, s));
+  const int bw = p->beam_width;
+  auto slot = [&](int i) { return c->pslots + (size_t)i * c->slot_stride; };
+  auto msg_of = [&](int i) { return (float*)slot(i); };
+  auto bits_of = [&](int i) { return (uint32_t*)(slot(i) + slot_ehat_off(g)); };
+  const int keeper = 3 * bw;
+  int64_t runs = 0, iters = 0, deep = 0;
+  HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+  for (int64_t q = 0; q < shots; ++q) {
+    const uint8_t* sq = syn + q * g.m;
+    EmitArgs e{};
+    e.g = g;
+    e.corr = corr + q * g.n;
+    e.flips = flips + q * g.k;
+    e.conv = conv + q;
+    RunOut r0;
+    st = plain_run(c, s, nullptr, {}, sq, p->initial_iters, p->alpha, msg_of(0), bits_of(keeper), &r0);
+    if (st != BSD_OK) return st;
+    ++runs;
+    iters += r0.iters;
+    int emit_slot = keeper, emit_conv = r0.conv;
+    if (!r0.conv && p->max_rounds > 0) {
+      ++deep;
+      std::vector<HostPath> set{{0, {}, r0.next_pos, 0.f, 0}};
+      std::vector<int> free_slots;
+      for (int i = 3 * bw - 1; i >= 1; --i) free_slots.push_back(i);
+      bool done = false;
+      for (int rd = 1; rd <= p->max_rounds && !done; ++rd) {
+        std::stable_sort(set.begin(), set.end(), [](const HostPath& a, const HostPath& b) {
+          if (a.score != b.score) return a.score > b.score;
+          return a.gen < b.gen;
+        });
+        std::vector<HostPath> kids;
+        for (size_t k = 0; k < set.size() && !done; ++k) {
+          if (set[k].next_pos < 0) continue;
+          for (int v = 0; v <= 1 && !done; ++v) {
+            HostPath ch;
+            ch.pairs = set[k].pairs;
+            ch.pairs.push_back((set[k].next_pos << 1) | v);
+            ch.gen = (int)(2 * k + v);
+            ch.slot = free_slots.back();
+            free_slots.pop_back();
+            RunOut rr;
+            st = plain_run(c, s, msg_of(set[k].slot), ch.pairs, sq, p->iters_per_round, p->alpha,
+                           msg_of(ch.slot), bits_of(ch.slot), &rr);
+            if (st != BSD_OK) return st;
+            ++runs;
+            iters += rr.iters;
+            if (rr.conv) {
+              emit_slot = ch.slot;
+              emit_conv = 1;
+              done = true;
+              break;
+            }
+            ch.next_pos = rr.next_pos;
+            ch.score = rr.score;
+            kids.push_back(ch);
+          }
+        }
+        if (done) break;
+        std::stable_sort(kids.begin(), kids.end(), [](const HostPath& a, const HostPath& b) {
+          if (a.score != b.score) return a.score > b.score;
+          return a.gen < b.gen;
+        });
+        for (const HostPath& par : set) free_slots.push_back(par.slot);
+        for (size_t k = (size_t)bw; k < kids.size(); ++k) free_slots.push_back(kids[k].slot);
+        if (kids.size() > (size_t)bw) kids.resize(bw);
+        set = std::move(kids);
+        if (rd == p->max_rounds) {
+          emit_slot = set.empty() ? keeper : set[0].slot;
+          emit_conv = 0;
+        } else {
+          bool any = false;
+          for (const HostPath& h : set) any |= h.next_pos >= 0;
+          if (!any) {
+            emit_slot = keeper;
+            emit_conv = 0;
+            break;
+          }
+        }
+      }
+    }
+    e.ehat_bits = bits_of(emit_slot);
+    e.converged = emit_conv;
+    HIP_OR_FAIL(launch_emit(e, s));
+  }
+  HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+  uint32_t err = 0;
+  HIP_OR_FAIL(hipMemcpyAsync(c->h_pinned + kMaxRounds + 4, c->d_error, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  std::memcpy(&err, c->h_pinned + kMaxRounds + 4, 4);
+  if (err) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  if (stats) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    stats->runs = runs;
+    stats->iterations = iters;
+    stats->edge_updates = iters * (int64_t)g.nnz;
+    stats->deep_shots = deep;
+    stats->kernel_ms = ms;
+  }
+  return BSD_OK;
+}
+
+bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                          uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
+                          bsd_stats* stats, uint32_t* lat) {
+  bsd_status st = ensure_batched(c, p->beam_width);
+  if (st != BSD_OK) return st;
+  BatchArgs a{};
+  a.g = c->g;
+  a.shots = shots;
+  a.syn = syn;
+  a.corr = corr;
+  a.flips = flips;
+  a.conv = conv;
+  a.lat = lat;
+  a.max_rounds = p->max_rounds;
+  a.bw = p->beam_width;
+  a.init_iters = p->initial_iters;
+  a.round_iters = p->iters_per_round;
+  a.num_results = p->num_results;
+  a.alpha = p->alpha;
+  a.st = c->st;
+  a.work_ring = c->work_ring;
+  a.work_cap = c->work_cap;
+  a.ctx_ring = c->ctx_ring;
+  a.ctx_cap = c->ctx_cap;
+  a.ctxs = c->ctxs;
+  a.nctx = c->nctx;
+  a.slots = c->slots;
+  a.slot_stride = c->slot_stride;
+  a.slots_per_ctx = 3 * c->ws_bw + 1;
+  HIP_OR_FAIL(launch_batch_reset(a, s));
+  HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+  HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->lds, s));
+  HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+  HIP_OR_FAIL(hipMemcpyAsync(c->st_host, c->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  const BatchState& h = *c->st_host;
+  if (h.error) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  if (h.done != (unsigned long long)shots)
+    return fail(BSD_EDEVICE, "batched decoder finished %llu of %lld shots", h.done, (long long)shots);
+  if (stats) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    stats->runs = (int64_t)h.runs;
+    stats->iterations = (int64_t)h.iterations;
+    stats->edge_updates = (int64_t)h.iterations * c->g.nnz;
+    stats->deep_shots = (int64_t)h.deep;
+    stats->kernel_ms = ms;
+  }
+  return BSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bsd_last_error(void) { return g_err.c_str(); }
+
+const char* bsd_version(void) { return "bsd-mi355x 0.1 (gfx950)"; }
+
+bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_colptr,
+                           const int32_t* h_rowidx, const double* p, const int32_t* l_colptr,
+                           const int32_t* l_rowidx, bsd_code* out) {
+  if (!out) return fail(BSD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (m <= 0 || n <= 0 || k < 0) return fail(BSD_EINVAL, "m, n must be > 0 and k >= 0");
+  if (m >= 65536) return fail(BSD_EINVAL, "m must be < 65536");
+  if (k > 64) return fail(BSD_EINVAL, "k must be <= 64");
+  if (!h_colptr || !h_rowidx || !p) return fail(BSD_EINVAL, "H and p are required");
+  if (k > 0 && (!l_colptr || !l_rowidx)) return fail(BSD_EINVAL, "A is required when k > 0");
+  if (h_colptr[0] != 0) return fail(BSD_EINVAL, "h_colptr[0] must be 0");
+  for (int j = 0; j < n; ++j) {
+    const int d = h_colptr[j + 1] - h_colptr[j];
+    if (d < 0) return fail(BSD_EINVAL, "h_colptr is not non-decreasing at column %d", j);
+    if (d > kMaxDv) return fail(BSD_EINVAL, "column %d has degree %d > %d", j, d, kMaxDv);
+    for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+      if (h_rowidx[e] < 0 || h_rowidx[e] >= m)
+        return fail(BSD_EINVAL, "row index out of range in column %d", j);
+      if (e > h_colptr[j] && h_rowidx[e] <= h_rowidx[e - 1])
+        return fail(BSD_EINVAL, "rows of column %d are not strictly ascending", j);
+    }
+    if (!(p[j] > 0.0 && p[j] < 1.0)) return fail(BSD_EINVAL, "p[%d] is not in (0,1)", j);
+  }
+  const int nnz = h_colptr[n];
+  if (nnz <= 0) return fail(BSD_EINVAL, "H has no edges");
+  if (k > 0) {
+    if (l_colptr[0] != 0) return fail(BSD_EINVAL, "l_colptr[0] must be 0");
+    for (int j = 0; j < n; ++j) {
+      if (l_colptr[j + 1] < l_colptr[j]) return fail(BSD_EINVAL, "l_colptr decreasing at %d", j);
+      for (int e = l_colptr[j]; e < l_colptr[j + 1]; ++e)
+        if (l_rowidx[e] < 0 || l_rowidx[e] >= k)
+          return fail(BSD_EINVAL, "logical row index out of range in column %d", j);
+    }
+  }
+  // Rows by descending degree (ties: ascending row), jagged diagonals.
+  std::vector<int> rdeg(m, 0);
+  for (int e = 0; e < nnz; ++e) rdeg[h_rowidx[e]]++;
+  std::vector<int> order(m);
+  for (int i = 0; i < m; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rdeg[a] > rdeg[b]; });
+  const int maxdeg = rdeg[order[0]];
+  if (maxdeg > kMaxDc) return fail(BSD_EINVAL, "a row has degree %d > %d", maxdeg, kMaxDc);
+  std::vector<int> rank_of_row(m);
+  std::vector<uint16_t> row_of_rank(m);
+  std::vector<uint8_t> deg_of_rank(m);
+  for (int r = 0; r < m; ++r) {
+    rank_of_row[order[r]] = r;
+    row_of_rank[r] = (uint16_t)order[r];
+    deg_of_rank[r] = (uint8_t)rdeg[order[r]];
+  }
+  std::vector<int32_t> diag_ptr(maxdeg + 1, 0);
+  for (int kk = 0; kk < maxdeg; ++kk) {
+    int cnt = 0;
+    while (cnt < m && rdeg[order[cnt]] > kk) ++cnt;
+    diag_ptr[kk + 1] = diag_ptr[kk] + cnt;
+  }
+  if (diag_ptr[maxdeg] != nnz) return fail(BSD_EINVAL, "internal: diagonal layout mismatch");
+  std::vector<int> seen(m, 0);
+  std::vector<uint32_t> cedge(nnz), colinfo(n);
+  for (int j = 0; j < n; ++j) {
+    colinfo[j] = (uint32_t)h_colptr[j] | ((uint32_t)(h_colptr[j + 1] - h_colptr[j]) << 24);
+    for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+      const int i = h_rowidx[e];
+      const int pos = diag_ptr[seen[i]++] + rank_of_row[i];
+      cedge[e] = (uint32_t)pos | ((uint32_t)rank_of_row[i] << 16);
+    }
+  }
+  std::vector<float> lam(n);
+  for (int j = 0; j < n; ++j) lam[j] = (float)std::log((1.0 - p[j]) / p[j]);
+  std::vector<uint64_t> lmask(n, 0);
+  for (int j = 0; j < n && k > 0; ++j)
+    for (int e = l_colptr[j]; e < l_colptr[j + 1]; ++e) lmask[j] ^= 1ull << l_rowidx[e];
+
+  bsd_code c = new (std::nothrow) bsd_code_s;
+  if (!c) return fail(BSD_ENOMEM, "host allocation failed");
+  HIP_OR_FAIL(hipGetDevice(&c->device));
+  DevGraph& g = c->g;
+  g.m = m;
+  g.n = n;
+  g.nnz = nnz;
+  g.k = k;
+  g.nnz_pad = (nnz + 3) & ~3;
+  g.words_m = (((m + 31) / 32) + 1) & ~1;
+  g.words_n = (((n + 31) / 32) + 1) & ~1;
+  g.maxdeg_row = maxdeg;
+  c->colptr.assign(h_colptr, h_colptr + n + 1);
+  c->rowidx.assign(h_rowidx, h_rowidx + nnz);
+  int32_t* d_diag;
+  uint16_t* d_ror;
+  uint8_t* d_dor;
+  uint32_t *d_ci, *d_ce;
+  float* d_lam;
+  uint64_t* d_lm;
+  if (dev_upload(&d_diag, diag_ptr) != hipSuccess || dev_upload(&d_ror, row_of_rank) != hipSuccess ||
+      dev_upload(&d_dor, deg_of_rank) != hipSuccess || dev_upload(&d_ci, colinfo) != hipSuccess ||
+      dev_upload(&d_ce, cedge) != hipSuccess || dev_upload(&d_lam, lam) != hipSuccess ||
+      dev_upload(&d_lm, lmask) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(BSD_ENOMEM, "cannot upload the graph");
+  }
+  c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_lam, d_lm};
+  g.diag_ptr = d_diag;
+  g.row_of_rank = d_ror;
+  g.deg_of_rank = d_dor;
+  g.colinfo = d_ci;
+  g.cedge = d_ce;
+  g.lambda = d_lam;
+  g.lmask = d_lm;
+
+  // Launch geometry: one BP run per workgroup; columns c * block + tid.
+  c->lds = lds_bytes_for(g, 0, 0);
+  if (c->lds > (size_t)kLdsBytes || nnz > 65535) {
+    bsd_code_destroy(c);
+    return fail(BSD_EINVAL, "graph too large: %d edges need %zu bytes of LDS (limit %d)", nnz,
+                c->lds, kLdsBytes);
+  }
+  if (c->lds > 64 * 1024) {
+    c->block = 1024;
+  } else {
+    c->block = 64;
+    while ((n + c->block - 1) / c->block > kMaxCpt) c->block *= 2;
+  }
+  c->cpt = (n + c->block - 1) / c->block;
+  if (c->cpt > kMaxCpt) {
+    bsd_code_destroy(c);
+    return fail(BSD_EINVAL, "n = %d too large (limit %d)", n, kMaxCpt * 1024);
+  }
+  hipError_t he = set_kernel_limits(c->cpt, c->lds);
+  if (he != hipSuccess) {
+    bsd_code_destroy(c);
+    return fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
+  }
+  int per_cu = 0, ncu = 0;
+  he = batched_occupancy(c->cpt, c->block, c->lds, &per_cu);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (he != hipSuccess || per_cu < 1) {
+    bsd_code_destroy(c);
+    return fail(BSD_EDEVICE, "occupancy query failed: %s (blocks per CU %d)", hipGetErrorString(he), per_cu);
+  }
+  c->grid = per_cu * ncu;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    bsd_code_destroy(c);
+    return fail(BSD_EDEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return BSD_OK;
+}
+
+bsd_status bsd_code_destroy(bsd_code c) {
+  if (!c) return BSD_OK;
+  if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
+  free_workspace(c);
+  for (void* p : c->owned) hipFree(p);
+  hipFree(c->pslots);
+  hipFree(c->d_pairs);
+  hipFree(c->d_result);
+  hipFree(c->d_error);
+  hipHostFree(c->h_pinned);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+  return BSD_OK;
+}
+
+bsd_status bsd_code_info(bsd_code c, int64_t* nnz, int32_t* block, int32_t* grid, int32_t* lds) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  if (nnz) *nnz = c->g.nnz;
+  if (block) *block = c->block;
+  if (grid) *grid = c->grid;
+  if (lds) *lds = (int32_t)c->lds;
+  return BSD_OK;
+}
+
+bsd_status bsd_decode_ex(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                         uint8_t* corr, uint8_t* flips, uint8_t* conv, void* stream,
+                         bsd_stats* stats, uint32_t* lat) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  bsd_status st = check_params(c, p);
+  if (st != BSD_OK) return st;
+  if (shots < 0) return fail(BSD_EINVAL, "shots must be >= 0");
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (shots == 0) return BSD_OK;
+  if (shots > (int64_t)0x7FFFFFFF) return fail(BSD_EINVAL, "at most 2^31-1 shots per call");
+  if (!syn || !corr || !conv || (c->g.k > 0 && !flips))
+    return fail(BSD_EINVAL, "syndromes, corrections, logical_flips and converged are required");
+  std::lock_guard<std::mutex> lock(c->mu);
+  c->busy++;
+  int dev_prev = 0;
+  (void)hipGetDevice(&dev_prev);
+  (void)hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  st = p->mode == BSD_MODE_PLAIN ? decode_plain(c, p, shots, syn, corr, flips, conv, s, stats)
+                                 : decode_batched(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+  (void)hipSetDevice(dev_prev);
+  c->busy--;
+  return st;
+}
+
+bsd_status bsd_decode(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                      uint8_t* corr, uint8_t* flips, uint8_t* conv, void* stream) {
+  return bsd_decode_ex(c, p, shots, syn, corr, flips, conv, stream, nullptr, nullptr);
+}
+
+bsd_status bsd_bp_run(bsd_code c, const float* e_start, const int32_t* pairs, int32_t npairs,
+                      const uint8_t* syndrome, int32_t max_iters, float alpha,
+                      int32_t stop_on_converge, float* e_out, float* sum_llr, uint8_t* ehat,
+                      int32_t* iters, int32_t* converged, int32_t* next_pos, float* score,
+                      void* stream) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  if (!syndrome) return fail(BSD_EINVAL, "syndrome is NULL");
+  if (max_iters < 0) return fail(BSD_EINVAL, "max_iters must be >= 0");
+  if (npairs < 0 || npairs > kMaxRounds) return fail(BSD_EINVAL, "npairs must be in [0, %d]", kMaxRounds);
+  if (npairs > 0 && !pairs) return fail(BSD_EINVAL, "pairs is NULL");
+  if (!(alpha > 0.f) || !std::isfinite(alpha)) return fail(BSD_EINVAL, "alpha must be positive and finite");
+  std::vector<int32_t> packed(npairs);
+  for (int q = 0; q < npairs; ++q) {
+    const int col = pairs[2 * q], val = pairs[2 * q + 1];
+    if (col < 0 || col >= c->g.n || (val != 0 && val != 1))
+      return fail(BSD_EINVAL, "pair %d = (%d, %d) is invalid", q, col, val);
+    for (int r = 0; r < q; ++r)
+      if ((packed[r] >> 1) == col) return fail(BSD_EINVAL, "column %d is masked twice", col);
+    packed[q] = (col << 1) | val;
+  }
+  std::lock_guard<std::mutex> lock(c->mu);
+  bsd_status st = ensure_plain(c, 0);
+  if (st != BSD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(hipMemsetAsync(c->d_error, 0, 4, s));
+  if (npairs) {
+    std::memcpy(c->h_pinned, packed.data(), npairs * 4);
+    HIP_OR_FAIL(hipMemcpyAsync(c->d_pairs, c->h_pinned, npairs * 4, hipMemcpyHostToDevice, s));
+  }
+  SingleArgs a{};
+  a.g = c->g;
+  a.parent_csc = e_start;
+  a.pairs = c->d_pairs;
+  a.npairs = npairs;
+  a.syn = syndrome;
+  a.max_iters = max_iters;
+  a.stop = stop_on_converge ? 1 : 0;
+  a.alpha = alpha;
+  a.want_score = 1;
+  a.out_csc = e_out;
+  a.out_sumllr = sum_llr;
+  a.out_ehat = ehat;
+  a.result = c->d_result;
+  a.error = c->d_error;
+  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->lds, s));
+  int32_t* res = c->h_pinned + kMaxRounds;
+  HIP_OR_FAIL(hipMemcpyAsync(res, c->d_result, 16, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipMemcpyAsync(res + 4, c->d_error, 4, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  if (res[4]) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  if (iters) *iters = res[0];
+  if (converged) *converged = res[1];
+  if (next_pos) *next_pos = res[2];
+  if (score) std::memcpy(score, &res[3], 4);
+  return BSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal layout shared by the decoder's kernels and its host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bsd {
+
+constexpr int kMaxDv = 8;          // largest column degree handled
+constexpr int kMaxDc = 255;        // largest row degree handled
+constexpr int kMaxBw = 64;         // largest beam width
+constexpr int kMaxRounds = 64;     // largest number of fixed nodes on a path
+constexpr int kMaxResults = 64;    // largest num_results
+constexpr int kMaxWaves = 16;      // 1024 threads per workgroup at most
+constexpr int kMaxCpt = 16;        // columns per thread at most
+constexpr float kLlrMax = 1e30f;   // saturation of every message
+constexpr int kLdsBytes = 160 * 1024;
+
+// Device-resident Tanner graph.  Rows are renumbered by "rank" (descending
+// degree); the LDS message of the edge (row of rank r, k-th neighbour in
+// ascending column order) lives at position diag_ptr[k] + r (jagged
+// diagonals), so that lanes holding consecutive ranks touch consecutive
+// words in the check phase.
+struct DevGraph {
+  int32_t m, n, nnz, k;
+  int32_t nnz_pad;      // nnz rounded up to a multiple of 4 (16-byte vector copies)
+  int32_t words_m;      // 32-bit words of a row bit-vector, rounded up to a multiple of 2
+  int32_t words_n;      // 32-bit words of a column bit-vector, rounded up to a multiple of 2
+  int32_t maxdeg_row;
+  const int32_t* diag_ptr;     // [maxdeg_row + 1]
+  const uint16_t* row_of_rank; // [m] original row of each rank
+  const uint8_t* deg_of_rank;  // [m]
+  const uint32_t* colinfo;     // [n] first CSC edge (bits 0..23) | degree << 24
+  const uint32_t* cedge;       // [nnz] CSC order: LDS position (bits 0..15) | row rank << 16
+  const float* lambda;         // [n] prior LLRs
+  const uint64_t* lmask;       // [n] logical rows flipped by each column
+};
+
+// One device-resident path (a beam "slot"): its edge messages in LDS order,
+// the hard decision of its last iteration, and its fixed nodes.
+//   float    msg[nnz_pad]
+//   uint32_t ehat[words_n]
+//   int32_t  npairs, pad[3]
+//   int32_t  pairs[kMaxRounds]   packed (column << 1) | value
+inline __host__ __device__ size_t slot_ehat_off(const DevGraph& g) { return (size_t)g.nnz_pad * 4; }
+inline __host__ __device__ size_t slot_pairs_off(const DevGraph& g) {
+  return slot_ehat_off(g) + (size_t)g.words_n * 4;
+}
+inline __host__ __device__ size_t slot_bytes(const DevGraph& g) {
+  size_t b = slot_pairs_off(g) + 16 + 4 * kMaxRounds;
+  return (b + 255) & ~(size_t)255;
+}
+
+// A shot whose initial BP run failed: the beam of Algorithm 3 in flight.
+struct Ctx {
+  int32_t shot;
+  int32_t round;          // round whose children are running (1-based)
+  int32_t nset;           // paths in the current set (parents of this round)
+  int32_t pending;        // children of this round not yet finished
+  int32_t best_gen;       // smallest converged child generation this round
+  int32_t nresults;
+  uint32_t t_start;       // device clock at the start of the initial run
+  int32_t pad0;
+  int32_t slots[3 * kMaxBw];          // first nset: parents in rank order; rest free
+  int32_t parent_next_pos[kMaxBw];
+  float child_score[2 * kMaxBw];
+  int32_t child_next_pos[2 * kMaxBw];
+  int32_t child_state[2 * kMaxBw];    // 0 ran, 1 converged, 2 cancelled
+  uint32_t init_ehat_off;             // unused padding kept for alignment
+  int32_t pad1[3];
+};
+
+// Multi-producer multi-consumer ring of 32-bit items (item + 1 stored; 0 = empty).
+struct Ring {
+  uint32_t head;
+  uint32_t tail;
+  int32_t count;
+  uint32_t cap;
+};
+
+struct BatchState {
+  unsigned long long next_shot;
+  unsigned long long done;
+  unsigned long long runs;
+  unsigned long long iterations;
+  unsigned long long deep;
+  uint32_t error;
+  uint32_t pad;
+  Ring work;
+  Ring ctxq;
+};
+
+struct BatchArgs {
+  DevGraph g;
+  long long shots;
+  const uint8_t* syn;
+  uint8_t* corr;
+  uint8_t* flips;
+  uint8_t* conv;
+  uint32_t* lat;
+  int32_t max_rounds, bw, init_iters, round_iters, num_results;
+  float alpha;
+  BatchState* st;
+  uint32_t* work_ring;
+  uint32_t work_cap;      // power of two
+  uint32_t* ctx_ring;
+  uint32_t ctx_cap;       // power of two
+  Ctx* ctxs;
+  int32_t nctx;
+  char* slots;            // nctx * slots_per_ctx slots
+  size_t slot_stride;
+  int32_t slots_per_ctx;  // 3 * bw + 1 (the last one keeps the initial run's hard decision)
+};
+
+// Arguments of a single BP run launched on its own (plain form, bsd_bp_run).
+struct SingleArgs {
+  DevGraph g;
+  const float* parent;      // warm start in LDS order, or NULL
+  const float* parent_csc;  // warm start in CSC order, or NULL
+  const int32_t* pairs;     // device, packed (col << 1) | val
+  int32_t npairs;
+  const uint8_t* syn;       // [m]
+  int32_t max_iters;
+  int32_t stop;
+  float alpha;
+  int32_t want_score;
+  float* out_msg;           // LDS order, written when not converged (or NULL)
+  float* out_csc;           // CSC order (or NULL)
+  float* out_sumllr;        // [n] (or NULL)
+  uint8_t* out_ehat;        // [n] bytes (or NULL)
+  uint32_t* out_ehat_bits;  // [words_n] (or NULL)
+  int32_t* out_pairs;       // [1 + kMaxRounds]: npairs, pairs (or NULL)
+  int32_t* result;          // [4]: iters, converged, next_pos, score bits
+  uint32_t* error;
+};
+
+// Final output of a shot from a hard-decision bit-vector (plain form).
+struct EmitArgs {
+  DevGraph g;
+  const uint32_t* ehat_bits;
+  const int32_t* fill_pairs; // packed pairs to fill in, or NULL
+  int32_t nfill;
+  uint8_t* corr;             // [n]
+  uint8_t* flips;            // [k]
+  uint8_t* conv;             // [1]
+  int32_t converged;
+};
+
+// Host-side launchers implemented in bsd_kernels.hip.
+hipError_t launch_single(const SingleArgs& a, int block, int cpt, size_t lds, hipStream_t s);
+hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, size_t lds,
+                          hipStream_t s);
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
+hipError_t set_kernel_limits(int cpt, size_t lds);
+hipError_t batched_occupancy(int cpt, int block, size_t lds, int* blocks_per_cu);
+
+size_t lds_bytes_for(const DevGraph& g, int block, int cpt);
+
+}  // namespace bsd
