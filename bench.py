@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched GPU beam-search decoder on one MI355X.
+
+Workload: the [[144,12,12]] bivariate bicycle code's 12-round space-time
+detector graph (936 detectors x 8592 fault columns, 37303 edges, priors
+log-uniform in [1e-5, 1e-3]); 1e5 seeded synthetic syndromes; decoder
+beam32_340iters (max_rounds 10, beam_width 32, initial_iters 40,
+iters_per_round 30) with scaling 0.625 and fp32 messages.
+
+A step decodes the whole batch (syndromes already in device memory) with
+one call of the batched persistent decoder.  Printed as one JSON line:
+shots/s, per-shot device decode latency percentiles, the plain
+one-launch-per-BP-run form's shots/s on a prefix of the same syndromes, the
+roofline position of the decoding kernel and the CPU oracle's rate on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shots/sec + p99.9 decode latency, BB144 12-round, beam 32; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bsd_batched_w2.json")
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("bsd_kernels.hip", "bsd_internal.h", "bsd_host.hip"):
+        with open(os.path.join(ROOT, "paper_2512_07057_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(units_bytes_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(pr, params, syn_all, target_s=10.0):
+    import oracle
+    op = oracle.OracleProblem.from_problem(pr)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    probe = min(2000, len(syn_all))
+    t0 = time.perf_counter()
+    op.decode_params(syn_all[:probe], params, dtype=np.float64, threads=cores)
+    dt = time.perf_counter() - t0
+    n = int(min(len(syn_all), max(probe, probe * target_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    op.decode_params(syn_all[:n], params, dtype=np.float64, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "shots/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of the benchmark's syndromes, double-precision oracle, "
+                      f"one shot per thread over {cores} host threads, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--shots", type=int, default=100_000)
+    ap.add_argument("--plain-shots", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(shots shard across GPUs with no exchange, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_07057_amd as bsd
+    from bsd_inputs import workloads
+
+    wl = workloads.WORKLOADS["W2"]
+    P = wl.params
+    pr = workloads.problem(wl.problem_key)
+    data = workloads.shots_for(wl, shots=args.shots)
+    syn_h = np.ascontiguousarray(data["syndromes"])
+    dev = torch.device("cuda:0")
+    code = bsd.Code.from_problem(pr)
+    info = code.info()
+    syn = torch.from_numpy(syn_h).to(dev)
+    shots = syn.shape[0]
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    out = {
+        "corrections": torch.empty((shots, pr.n), dtype=torch.uint8, device=dev),
+        "flips": torch.empty((shots, pr.k), dtype=torch.uint8, device=dev),
+        "converged": torch.empty((shots,), dtype=torch.uint8, device=dev),
+    }
+    prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                          P.num_results, P.alpha, bsd.MODE_BATCHED)
+    for _ in range(args.warmup):
+        code.decode(syn, prm, out=out)
+    torch.cuda.synchronize()
+    kernel_ms, iters = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = code.decode(syn, prm, out=out)
+        kernel_ms.append(r["stats"]["kernel_ms"])
+        iters.append(r["stats"]["iterations"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = shots / (ms_per_step / 1e3)
+
+    # Per-shot device latency and the logical error rate, from one more call.
+    r = code.decode(syn, prm, out=out, latency=True)
+    torch.cuda.synchronize()
+    lat_us = r["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0  # 100 MHz clock
+    conv = out["converged"].cpu().numpy().astype(bool)
+    fails = (~conv) | (out["flips"].cpu().numpy() != data["true_flips"]).any(1)
+
+    # Plain form: one kernel launch per BP run, beam bookkeeping on the host.
+    nplain = min(args.plain_shots, shots)
+    prm_plain = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                                P.num_results, P.alpha, bsd.MODE_PLAIN)
+    code.decode(syn[:64].contiguous(), prm_plain)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    rp = code.decode(syn[:nplain].contiguous(), prm_plain)
+    torch.cuda.synchronize()
+    plain_rate = nplain / (time.perf_counter() - tp)
+    same = bool((rp["corrections"] == out["corrections"][:nplain]).all().item())
+
+    # Roofline of the batched kernel: algorithmic bytes of the two-phase
+    # min-sum form (E read and written per edge, sum_LLR read and written per
+    # column, every iteration of every run) over the kernel's event time.
+    bytes_per_iter = 8 * pr.nnz + 8 * pr.n
+    alg_bytes = float(np.mean(iters)) * bytes_per_iter
+    kms = float(np.mean(kernel_ms))
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alg_bytes)}
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "W2: [[144,12,12]] BB code 12-round space-time graph "
+                               "(936 detectors x 8592 columns, 37303 edges), priors log-uniform "
+                               "[1e-5,1e-3], 1e5 seeded syndromes, beam32_340iters, alpha 0.625",
+                   "shots": shots, "beam_width": P.beam_width, "max_rounds": P.max_rounds,
+                   "initial_iters": P.initial_iters, "iters_per_round": P.iters_per_round,
+                   "block_threads": info["block"], "grid_blocks": info["grid"],
+                   "lds_bytes": info["lds_bytes"]},
+        "latency_us": {"p50": float(np.percentile(lat_us, 50)),
+                       "p99": float(np.percentile(lat_us, 99)),
+                       "p999": float(np.percentile(lat_us, 99.9)),
+                       "max": float(lat_us.max()),
+                       "what": "per shot, device clock from the start of its initial BP run "
+                               "to the write of its result, inside the batched kernel"},
+        "plain": {"shots_per_s": plain_rate, "shots": nplain, "identical_to_batched": same},
+        "batched_over_plain": value / plain_rate,
+        "kernel_ms": kms,
+        "edge_updates_per_s": float(np.mean(iters)) * pr.nnz / (kms * 1e-3),
+        "bp_iterations_per_step": float(np.mean(iters)),
+        "ler": float(fails.mean()),
+        "converged_frac": float(conv.mean()),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(pr, P, syn_h)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
