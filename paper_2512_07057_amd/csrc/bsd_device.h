@@ -1,0 +1,990 @@
+// Device code of the beam-search decoder for gfx950 (templates; instantiated
+// per column-position word count PW in bsd_kernels_pw*.hip).
+//
+// One workgroup runs one BP run at a time with the run's edge messages held
+// in LDS (fp32, one word per Tanner edge, jagged-diagonal order).  A run is
+// the masked min-sum BP of Algorithm 2: eq. (1) in the check phase (one lane
+// per detector row), eqs. (2)-(4) in the variable phase (lanes own columns
+// c * blockDim + tid), the stopping rule through an LDS residual bit-vector,
+// and, when a run fails, the path score and least reliable node of
+// Algorithm 3.  The graph data a lane needs (LDS positions of its columns'
+// edges, degrees, priors, the rows it checks) is read once per launch into
+// registers, so a run touches only LDS apart from its syndrome, its
+// warm-start messages and its results.
+//
+// Floating-point order follows the paper's formulas left to right: sums run
+// over neighbours in ascending row index, E of eq. (2) is a literal exclusive
+// sum (the shared prefix is reused, the skipped term is never added and
+// subtracted), sum_LLR accumulates in iteration order, and the path score
+// sums |sum_LLR| as an aligned pairwise tree over column index.  Built with
+// -ffp-contract=off.
+#pragma once
+
+#include "bsd_internal.h"
+
+namespace bsd {
+namespace dev {
+
+constexpr int AGENT = __HIP_MEMORY_SCOPE_AGENT;
+constexpr uint32_t kInfBits = 0x7F800000u;
+constexpr uint32_t kSignBit = 0x80000000u;
+
+struct LdsMap {
+  float* msg;
+  int32_t* diag;     // [maxdeg_row + 1] jagged-diagonal starts
+  uint32_t* sprime;  // masked syndrome s' by row rank
+  uint32_t* resid;   // s' xor H e-hat
+  int32_t* pairs;    // packed (col << 1) | val
+  float* redf;       // [kMaxCpt][kMaxWaves] score partials
+  float* aminv;      // [kMaxWaves]
+  int32_t* aminj;    // [kMaxWaves]
+  uint32_t* flw;     // [2 * kMaxWaves] logical flip partials
+  int32_t* misc;     // [32]
+  int32_t* order;    // [2 * kMaxBw] rank of each child
+  int32_t* byrank;   // [2 * kMaxBw] child of each rank
+  int32_t* mark;     // [3 * kMaxBw + 1]
+  int32_t* newslots; // [3 * kMaxBw]
+  float* part;       // [kMaxCpt]
+};
+
+__host__ __device__ inline size_t diag_words(const DevGraph& g) {
+  return ((size_t)g.maxdeg_row + 1 + 3) & ~(size_t)3;
+}
+
+__host__ __device__ inline size_t lds_tail_bytes(const DevGraph& g) {
+  return diag_words(g) * 4 + (size_t)g.words_m * 8 + kMaxRounds * 4 + kMaxCpt * kMaxWaves * 4 +
+         kMaxWaves * 8 + 2 * kMaxWaves * 4 + 32 * 4 + 4 * kMaxBw * 4 + (3 * kMaxBw + 1) * 4 +
+         3 * kMaxBw * 4 + kMaxCpt * 4;
+}
+
+__device__ __forceinline__ LdsMap lds_map(const DevGraph& g, char* lds) {
+  LdsMap L;
+  char* p = lds;
+  L.msg = (float*)p;
+  p += (size_t)g.nnz_pad * 4;
+  L.diag = (int32_t*)p;
+  p += diag_words(g) * 4;
+  L.sprime = (uint32_t*)p;
+  p += (size_t)g.words_m * 4;
+  L.resid = (uint32_t*)p;
+  p += (size_t)g.words_m * 4;
+  L.pairs = (int32_t*)p;
+  p += kMaxRounds * 4;
+  L.redf = (float*)p;
+  p += kMaxCpt * kMaxWaves * 4;
+  L.aminv = (float*)p;
+  p += kMaxWaves * 4;
+  L.aminj = (int32_t*)p;
+  p += kMaxWaves * 4;
+  L.flw = (uint32_t*)p;
+  p += 2 * kMaxWaves * 4;
+  L.misc = (int32_t*)p;
+  p += 32 * 4;
+  L.order = (int32_t*)p;
+  p += 2 * kMaxBw * 4;
+  L.byrank = (int32_t*)p;
+  p += 2 * kMaxBw * 4;
+  L.mark = (int32_t*)p;
+  p += (3 * kMaxBw + 1) * 4;
+  L.newslots = (int32_t*)p;
+  p += 3 * kMaxBw * 4;
+  L.part = (float*)p;
+  return L;
+}
+
+// Graph data of one lane, read once per launch.  Lane tid owns columns
+// c * B + tid (c < CPT) and detector rows of rank q * B + tid (q < 2).
+template <int CPT, int PW>
+struct Res {
+  float lam[CPT];
+  uint32_t pos[CPT][PW];          // LDS positions of the column's edges, 16 bits each, CSC order
+  uint32_t deg[(CPT + 7) / 8];    // 4 bits per column
+  uint32_t dmx[(CPT + 7) / 8];    // 4 bits per column: largest degree in the wave
+  uint32_t row[2];                // original row (16 bits) | degree << 16; 0xFFFFFFFF past m
+};
+
+template <int CPT>
+struct RunRegs {
+  float sumllr[CPT];
+  uint32_t ebits;  // hard decision of unmasked columns at the last iteration
+  uint32_t mbits;  // masked columns
+  uint32_t vbits;  // values of masked columns
+};
+
+struct RunRes {
+  int iters;
+  int conv;
+  int cancelled;
+};
+
+template <int CPT, int PW>
+__device__ __forceinline__ int col_deg(const Res<CPT, PW>& R, int c) {
+  return (int)((R.deg[c >> 3] >> (4 * (c & 7))) & 15u);
+}
+
+template <int CPT, int PW>
+__device__ __forceinline__ int col_dmax(const Res<CPT, PW>& R, int c) {
+  return __builtin_amdgcn_readfirstlane((int)((R.dmx[c >> 3] >> (4 * (c & 7))) & 15u));
+}
+
+template <int CPT, int PW>
+__device__ __forceinline__ uint32_t col_pos(const Res<CPT, PW>& R, int c, int e) {
+  return (R.pos[c][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Load a lane's graph data (called by every thread, before any run).
+template <int CPT, int PW>
+__device__ __forceinline__ void load_res(const DevGraph& g, const LdsMap& L, Res<CPT, PW>& R) {
+  const int tid = threadIdx.x, B = blockDim.x;
+  for (int i = tid; i <= g.maxdeg_row; i += B) L.diag[i] = g.diag_ptr[i];
+#pragma unroll
+  for (int w = 0; w < (CPT + 7) / 8; ++w) R.deg[w] = R.dmx[w] = 0u;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + tid;
+    int dg = 0;
+    R.lam[c] = 0.f;
+#pragma unroll
+    for (int w = 0; w < PW; ++w) R.pos[c][w] = 0u;
+    if (j < g.n) {
+      const uint32_t info = g.colinfo[j];
+      const int st = (int)(info & 0xFFFFFFu);
+      dg = (int)(info >> 24);
+      R.lam[c] = g.lambda[j];
+#pragma unroll
+      for (int e = 0; e < 2 * PW; ++e)
+        if (e < dg) R.pos[c][e >> 1] |= (g.cedge[st + e] & 0xFFFFu) << (16 * (e & 1));
+    }
+    R.deg[c >> 3] |= (uint32_t)dg << (4 * (c & 7));
+    R.dmx[c >> 3] |= (uint32_t)wave_max_i(dg) << (4 * (c & 7));
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = q * B + tid;
+    R.row[q] = r < g.m ? ((uint32_t)g.row_of_rank[r] | ((uint32_t)g.deg_of_rank[r] << 16))
+                       : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+}
+
+// Eq. (1) for the detector row of rank r, in place: E(t-1) -> D(t) on the
+// unmasked edges (masked edges hold +inf and are skipped).  Magnitudes of
+// non-negative floats compare as unsigned integers.
+__device__ __forceinline__ void check_row(const LdsMap& L, int r, int dg, float alpha) {
+  uint32_t* msg = reinterpret_cast<uint32_t*>(L.msg);
+  const int kmax = __builtin_amdgcn_readfirstlane(dg);  // ranks are sorted by degree
+  uint32_t sgn = ((L.sprime[r >> 5] >> (r & 31)) & 1u) << 31;
+  uint32_t m1 = __float_as_uint(kLlrMax), m2 = m1;
+  int arg = -1;
+  for (int k = 0; k < kmax; ++k) {
+    const int p = L.diag[k] + r;
+    if (k < dg) {
+      const uint32_t v = msg[p];
+      const uint32_t a = v & ~kSignBit;
+      sgn ^= v;
+      m2 = min(m2, max(m1, a));
+      arg = a < m1 ? k : arg;
+      m1 = min(m1, a);
+    }
+  }
+  const uint32_t d1 = __float_as_uint(fminf(alpha * __uint_as_float(m1), kLlrMax));
+  const uint32_t d2 = __float_as_uint(fminf(alpha * __uint_as_float(m2), kLlrMax));
+  for (int k = 0; k < kmax; ++k) {
+    const int p = L.diag[k] + r;
+    if (k < dg) {
+      const uint32_t v = msg[p];
+      if (v != kInfBits) msg[p] = (k == arg ? d2 : d1) | ((sgn ^ v) & kSignBit);
+    }
+  }
+}
+
+// Eqs. (2)-(4) for one column with at most D edges (D uniform over the wave).
+template <int D, int CPT, int PW>
+__device__ __forceinline__ void var_col(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
+                                        int c, bool active, float& sl, uint32_t& eb) {
+  const int dg = col_deg(R, c);
+  float d[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) d[e] = (active && e < dg) ? L.msg[col_pos(R, c, e)] : 0.f;
+  if (!active) return;
+  float pre = R.lam[c];
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    if (e < dg) {  // eq. (2): the prefix before e, then the terms after e
+      float x = pre;
+#pragma unroll
+      for (int f = e + 1; f < D; ++f) x = x + d[f];
+      L.msg[col_pos(R, c, e)] = fminf(fmaxf(x, -kLlrMax), kLlrMax);
+    }
+    pre = pre + d[e];
+  }
+  const float post = pre;  // eq. (3)
+  sl = sl + post;
+  eb = post <= 0.f ? 1u : 0u;  // eq. (4)
+  if (eb) {
+    const int j = c * (int)blockDim.x + (int)threadIdx.x;
+    const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
+    for (int e = 0; e < dg; ++e) {
+      const uint32_t rk = g.cedge[st + e] >> 16;
+      atomicXor(&L.resid[rk >> 5], 1u << (rk & 31));
+    }
+  }
+}
+
+template <int CPT, int PW>
+__device__ __forceinline__ void var_phase(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
+                                          RunRegs<CPT>& rg) {
+  const int B = blockDim.x;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + threadIdx.x;
+    const bool active = j < g.n && !((rg.mbits >> c) & 1u);
+    uint32_t eb = 0;
+    const int D = col_dmax(R, c);
+    if (D == 1) var_col<1>(g, L, R, c, active, rg.sumllr[c], eb);
+    else if (D == 2) var_col<2>(g, L, R, c, active, rg.sumllr[c], eb);
+    if constexpr (PW >= 2) {
+      if (D == 3) var_col<3>(g, L, R, c, active, rg.sumllr[c], eb);
+      else if (D == 4) var_col<4>(g, L, R, c, active, rg.sumllr[c], eb);
+    }
+    if constexpr (PW >= 3) {
+      if (D == 5) var_col<5>(g, L, R, c, active, rg.sumllr[c], eb);
+      else if (D == 6) var_col<6>(g, L, R, c, active, rg.sumllr[c], eb);
+    }
+    if constexpr (PW >= 4) {
+      if (D == 7) var_col<7>(g, L, R, c, active, rg.sumllr[c], eb);
+      else if (D == 8) var_col<8>(g, L, R, c, active, rg.sumllr[c], eb);
+    }
+    rg.ebits = (rg.ebits & ~(1u << c)) | (eb << c);
+  }
+}
+
+// One masked BP run (Algorithm 2).  The caller has placed `npairs` packed
+// pairs in L.pairs and synchronised.  Warm start from `parent` (LDS order) or
+// `parent_csc` (CSC order), else from the priors.  When `cancel` is given the
+// run stops early once *cancel < my_gen (a lower generation converged).
+template <int CPT, int PW>
+__device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
+                                         const float* parent, const float* parent_csc, int npairs,
+                                         const uint8_t* syn, int T, bool stop, float alpha,
+                                         const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
+                                         uint32_t* err) {
+  const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  rg.mbits = rg.vbits = rg.ebits = 0;
+  for (int q = 0; q < npairs; ++q) {
+    const int pv = L.pairs[q];
+    const int d = (pv >> 1) - tid;
+    if (d >= 0 && d % B == 0 && d / B < CPT) {
+      rg.mbits |= 1u << (d / B);
+      rg.vbits |= (uint32_t)(pv & 1) << (d / B);
+    }
+  }
+  // s by row rank, 64 ranks per wave ballot.
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint32_t bit = 0;
+    if (R.row[q] != 0xFFFFFFFFu) {
+      const uint32_t b = syn[R.row[q] & 0xFFFFu];
+      if (b > 1u) atomicOr(err, 1u);
+      bit = b & 1u;
+    }
+    const unsigned long long bal = __ballot(bit);
+    if (lane == 0) {
+      const int w = (q * B + wave * 64) >> 5;
+      if (w < g.words_m) L.sprime[w] = (uint32_t)bal;
+      if (w + 1 < g.words_m) L.sprime[w + 1] = (uint32_t)(bal >> 32);
+    }
+  }
+  if (parent) {
+    const float4* src = reinterpret_cast<const float4*>(parent);
+    float4* dst = reinterpret_cast<float4*>(L.msg);
+    for (int i = tid; i < g.nnz_pad / 4; i += B) dst[i] = src[i];
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    rg.sumllr[c] = 0.f;
+    const int j = c * B + tid;
+    if (!parent && j < g.n) {
+      const int dg = col_deg(R, c);
+      if (parent_csc) {
+        const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
+        for (int e = 0; e < dg; ++e) L.msg[g.cedge[st + e] & 0xFFFFu] = parent_csc[st + e] + 0.f;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2 * PW; ++e)
+          if (e < dg) L.msg[col_pos(R, c, e)] = R.lam[c];
+      }
+    }
+  }
+  __syncthreads();
+  // Masked nodes leave every check (+inf) and fold their value into s'.
+  if (npairs) {
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if ((rg.mbits >> c) & 1u) {
+        const int j = c * B + tid;
+        const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
+        for (int e = 0; e < dg; ++e) {
+          const uint32_t w = g.cedge[st + e];
+          L.msg[w & 0xFFFFu] = __builtin_inff();
+          if ((rg.vbits >> c) & 1u) {
+            const uint32_t rk = w >> 16;
+            atomicXor(&L.sprime[rk >> 5], 1u << (rk & 31));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  RunRes rr{0, 0, 0};
+  for (int t = 1; t <= T; ++t) {
+    for (int w = tid; w < g.words_m; w += B) L.resid[w] = L.sprime[w];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (R.row[q] != 0xFFFFFFFFu) check_row(L, q * B + tid, (int)(R.row[q] >> 16), alpha);
+    __syncthreads();
+    var_phase<CPT, PW>(g, L, R, rg);
+    __syncthreads();
+    int nz = 0;
+    for (int w = tid; w < g.words_m; w += B) nz |= (L.resid[w] != 0u);
+    if (tid == 0) {
+      int cx = 0;
+      if (cancel) cx = __hip_atomic_load(cancel, __ATOMIC_RELAXED, AGENT) < my_gen;
+      L.misc[0] = cx;
+    }
+    const int any = __syncthreads_or(nz);
+    rr.iters = t;
+    rr.conv = any ? 0 : 1;
+    if (stop && rr.conv) break;
+    if (L.misc[0]) {
+      rr.cancelled = 1;
+      break;
+    }
+  }
+  return rr;
+}
+
+// Path score and next branching node of a finished run (Algorithm 3):
+// next_pos = least |sum_LLR| over unmasked nodes (lowest index on ties),
+// score = aligned pairwise-tree sum of |sum_LLR| over unmasked nodes / iters.
+template <int CPT>
+__device__ __forceinline__ void score_next(const DevGraph& g, const LdsMap& L,
+                                           const RunRegs<CPT>& rg, int iters, float* score,
+                                           int* next_pos) {
+  const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+  float bv = __builtin_inff();
+  int bj = 0x7FFFFFFF;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + tid;
+    const bool ok = j < g.n && !((rg.mbits >> c) & 1u);
+    float a = ok ? fabsf(rg.sumllr[c]) : 0.f;
+    if (ok && a < bv) {
+      bv = a;
+      bj = j;
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) a = a + __shfl_xor(a, o, 64);
+    if (lane == 0) L.redf[c * kMaxWaves + wave] = a;
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float ov = __shfl_xor(bv, o, 64);
+    const int oj = __shfl_xor(bj, o, 64);
+    if (ov < bv || (ov == bv && oj < bj)) {
+      bv = ov;
+      bj = oj;
+    }
+  }
+  if (lane == 0) {
+    L.aminv[wave] = bv;
+    L.aminj[wave] = bj;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // Aligned pairwise tree: over the waves of each column block, then over blocks.
+    for (int c = 0; c < CPT; ++c) {
+      float* v = L.redf + c * kMaxWaves;
+      for (int len = nw; len > 1; len >>= 1)
+        for (int i = 0; i < len / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
+      L.part[c] = v[0];
+    }
+    int c2 = 1;
+    while (c2 < CPT) c2 <<= 1;
+    for (int c = CPT; c < c2; ++c) L.part[c] = 0.f;
+    for (int len = c2; len > 1; len >>= 1)
+      for (int i = 0; i < len / 2; ++i) L.part[i] = L.part[2 * i] + L.part[2 * i + 1];
+    const float sc = iters > 0 ? L.part[0] / (float)iters : 0.f;
+    float mv = __builtin_inff();
+    int mj = 0x7FFFFFFF;
+    for (int w = 0; w < nw; ++w) {
+      if (L.aminv[w] < mv || (L.aminv[w] == mv && L.aminj[w] < mj)) {
+        mv = L.aminv[w];
+        mj = L.aminj[w];
+      }
+    }
+    L.misc[4] = __float_as_int(sc);
+    L.misc[5] = (mj == 0x7FFFFFFF) ? -1 : mj;
+  }
+  __syncthreads();
+  *score = __int_as_float(L.misc[4]);
+  *next_pos = L.misc[5];
+  __syncthreads();
+}
+
+// Hard-decision bits (one bit per column) to a global bit-vector.
+template <int CPT>
+__device__ __forceinline__ void store_bits(const DevGraph& g, uint32_t* dst, uint32_t bits) {
+  const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + tid;
+    const unsigned long long bal = __ballot(j < g.n && ((bits >> c) & 1u));
+    if (lane == 0) {
+      const int w = (c * B + wave * 64) >> 5;
+      if (w < g.words_n) dst[w] = (uint32_t)bal;
+      if (w + 1 < g.words_n) dst[w + 1] = (uint32_t)(bal >> 32);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_msg(const DevGraph& g, const LdsMap& L, float* dst) {
+  const float4* src = reinterpret_cast<const float4*>(L.msg);
+  float4* d = reinterpret_cast<float4*>(dst);
+  for (int i = threadIdx.x; i < g.nnz_pad / 4; i += blockDim.x) d[i] = src[i];
+}
+
+// XOR-reduce per-lane 64-bit logical flip masks over the workgroup.
+__device__ __forceinline__ unsigned long long block_xor64(const LdsMap& L, unsigned long long f) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  uint32_t lo = (uint32_t)f, hi = (uint32_t)(f >> 32);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo ^= __shfl_xor(lo, o, 64);
+    hi ^= __shfl_xor(hi, o, 64);
+  }
+  if (lane == 0) {
+    L.flw[2 * wave] = lo;
+    L.flw[2 * wave + 1] = hi;
+  }
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int w = 0; w < nw; ++w)
+    t ^= (unsigned long long)L.flw[2 * w] | ((unsigned long long)L.flw[2 * w + 1] << 32);
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void write_flips(const DevGraph& g, unsigned long long t, uint8_t* flips) {
+  for (int r = threadIdx.x; r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
+}
+
+// Shot output from register-resident hard decisions (columns c*B + tid).
+template <int CPT>
+__device__ __forceinline__ void emit_from_regs(const DevGraph& g, const LdsMap& L, uint32_t bits,
+                                               uint8_t* corr, uint8_t* flips) {
+  const int B = blockDim.x;
+  unsigned long long f = 0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + threadIdx.x;
+    if (j < g.n) {
+      const uint32_t b = (bits >> c) & 1u;
+      corr[j] = (uint8_t)b;
+      if (b) f ^= g.lmask[j];
+    }
+  }
+  write_flips(g, block_xor64(L, f), flips);
+}
+
+// Shot output from a global bit-vector.
+__device__ __forceinline__ void emit_from_bits(const DevGraph& g, const LdsMap& L,
+                                               const uint32_t* bits, uint8_t* corr, uint8_t* flips) {
+  unsigned long long f = 0;
+  for (int j = threadIdx.x; j < g.n; j += blockDim.x) {
+    const uint32_t b = (bits[j >> 5] >> (j & 31)) & 1u;
+    corr[j] = (uint8_t)b;
+    if (b) f ^= g.lmask[j];
+  }
+  write_flips(g, block_xor64(L, f), flips);
+}
+
+// ---------------------------------------------------------------------------
+// Device queues: multi-producer multi-consumer rings of 32-bit items
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool ring_pop(Ring* r, uint32_t* buf, uint32_t* out) {
+  if (__hip_atomic_load(&r->count, __ATOMIC_RELAXED, AGENT) <= 0) return false;
+  const int c = __hip_atomic_fetch_add(&r->count, -1, __ATOMIC_ACQ_REL, AGENT);
+  if (c <= 0) {
+    __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELAXED, AGENT);
+    return false;
+  }
+  const uint32_t h = __hip_atomic_fetch_add(&r->head, 1u, __ATOMIC_RELAXED, AGENT) & (r->cap - 1u);
+  uint32_t x;
+  while ((x = __hip_atomic_load(&buf[h], __ATOMIC_ACQUIRE, AGENT)) == 0u) __builtin_amdgcn_s_sleep(2);
+  __hip_atomic_store(&buf[h], 0u, __ATOMIC_RELAXED, AGENT);
+  *out = x - 1u;
+  return true;
+}
+
+__device__ __forceinline__ void ring_push(Ring* r, uint32_t* buf, uint32_t item) {
+  const uint32_t t = __hip_atomic_fetch_add(&r->tail, 1u, __ATOMIC_RELAXED, AGENT) & (r->cap - 1u);
+  while (__hip_atomic_load(&buf[t], __ATOMIC_RELAXED, AGENT) != 0u) __builtin_amdgcn_s_sleep(2);
+  __hip_atomic_store(&buf[t], item + 1u, __ATOMIC_RELEASE, AGENT);
+  __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELEASE, AGENT);
+}
+
+__device__ __forceinline__ char* slot_ptr(const BatchArgs& a, int ctx, int s) {
+  return a.slots + ((size_t)ctx * a.slots_per_ctx + s) * a.slot_stride;
+}
+
+__device__ __forceinline__ uint32_t dev_clock() { return (uint32_t)wall_clock64(); }
+
+// Write the shot's outputs from a slot's hard-decision bits and retire the context.
+__device__ __forceinline__ void finish_deep(const BatchArgs& a, const LdsMap& L, int ctx,
+                                            long long shot, const uint32_t* bits, int converged,
+                                            uint32_t t_start) {
+  const DevGraph& g = a.g;
+  emit_from_bits(g, L, bits, a.corr + shot * g.n, a.flips + shot * g.k);
+  if (threadIdx.x == 0) {
+    a.conv[shot] = (uint8_t)converged;
+    if (a.lat) a.lat[shot] = dev_clock() - t_start;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ring_push(&a.st->ctxq, a.ctx_ring, (uint32_t)ctx);
+    __hip_atomic_fetch_add(&a.st->done, 1ull, __ATOMIC_RELEASE, AGENT);
+  }
+}
+
+// Selection at the end of a round (Algorithm 3 with Appendix B), run by the
+// workgroup that finished the round's last child.
+__device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L, int ctx) {
+  const DevGraph& g = a.g;
+  Ctx* C = a.ctxs + ctx;
+  const int tid = threadIdx.x;
+  const int nset = C->nset, round = C->round, best = C->best_gen;
+  const long long shot = C->shot;
+  const uint32_t t0 = C->t_start;
+  const int nch = 2 * nset;
+  if (best != 0x7FFFFFFF) {
+    // First converged child in exploration order.
+    const int s = C->slots[nset + best];
+    finish_deep(a, L, ctx, shot, (const uint32_t*)(slot_ptr(a, ctx, s) + slot_ehat_off(g)), 1, t0);
+    return;
+  }
+  // Rank the children by (score desc, generation asc); children of parents
+  // that could not branch do not exist.
+  for (int i = tid; i < nch; i += blockDim.x) {
+    int rank = -1;
+    if (C->parent_next_pos[i >> 1] >= 0) {
+      const float si = C->child_score[i];
+      rank = 0;
+      for (int q = 0; q < nch; ++q) {
+        if (q == i || C->parent_next_pos[q >> 1] < 0) continue;
+        const float sq = C->child_score[q];
+        if (sq > si || (sq == si && q < i)) ++rank;
+      }
+    }
+    L.order[i] = rank;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int cnt = 0;
+    int32_t* byrank = L.byrank;
+    for (int i = 0; i < nch; ++i)
+      if (L.order[i] >= 0) {
+        byrank[L.order[i]] = i;
+        ++cnt;
+      }
+    const int ns = cnt < a.bw ? cnt : a.bw;
+    int action;  // 0: next round, 1: fail with best survivor, 2: fail with the initial decision
+    int nbranch = 0;
+    if (round >= a.max_rounds) {
+      action = ns > 0 ? 1 : 2;
+    } else {
+      for (int q = 0; q < ns; ++q) nbranch += C->child_next_pos[byrank[q]] >= 0;
+      action = nbranch > 0 ? 0 : 2;
+    }
+    L.misc[8] = action;
+    L.misc[9] = ns > 0 ? C->slots[nset + byrank[0]] : 0;
+    if (action == 0) {
+      const int ntot = 3 * a.bw;
+      int32_t* newslots = L.newslots;
+      for (int s = 0; s < ntot; ++s) L.mark[s] = 0;
+      for (int q = 0; q < ns; ++q) {
+        const int c = byrank[q];
+        newslots[q] = C->slots[nset + c];
+        L.mark[newslots[q]] = 1;
+        C->parent_next_pos[q] = C->child_next_pos[c];
+      }
+      int k = ns;
+      for (int q = 0; q < ntot; ++q) {
+        const int s = C->slots[q];
+        if (!L.mark[s]) newslots[k++] = s;
+      }
+      for (int q = 0; q < ntot; ++q) C->slots[q] = newslots[q];
+      C->nset = ns;
+      C->round = round + 1;
+      C->best_gen = 0x7FFFFFFF;
+      C->pending = 2 * nbranch;
+      __threadfence();
+      for (int q = 0; q < ns; ++q)
+        if (C->parent_next_pos[q] >= 0) {
+          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q));
+          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q + 1));
+        }
+    }
+  }
+  __syncthreads();
+  const int action = L.misc[8];
+  const int s0 = L.misc[9];
+  __syncthreads();
+  if (action == 1) {
+    finish_deep(a, L, ctx, shot, (const uint32_t*)(slot_ptr(a, ctx, s0) + slot_ehat_off(g)), 0, t0);
+  } else if (action == 2) {
+    finish_deep(a, L, ctx, shot,
+                (const uint32_t*)(slot_ptr(a, ctx, 3 * a.bw) + slot_ehat_off(g)), 0, t0);
+  }
+}
+
+// Initial BP run of a shot.  `ctx` is the workgroup's spare context; the
+// return value tells whether the shot went deep and consumed it.
+template <int CPT, int PW>
+__device__ __forceinline__ bool process_init(const BatchArgs& a, const LdsMap& L,
+                                             const Res<CPT, PW>& R, long long shot, int ctx,
+                                             unsigned long long& nruns, unsigned long long& niters) {
+  const DevGraph& g = a.g;
+  const uint32_t t0 = dev_clock();
+  RunRegs<CPT> rg;
+  const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + shot * g.m,
+                                    a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error);
+  nruns += 1;
+  niters += rr.iters;
+  if (rr.conv || a.max_rounds == 0) {
+    emit_from_regs<CPT>(g, L, rg.ebits, a.corr + shot * g.n, a.flips + shot * g.k);
+    if (threadIdx.x == 0) {
+      a.conv[shot] = (uint8_t)rr.conv;
+      if (a.lat) a.lat[shot] = dev_clock() - t0;
+      __hip_atomic_fetch_add(&a.st->done, 1ull, __ATOMIC_RELAXED, AGENT);
+    }
+    return false;
+  }
+  float score;
+  int next_pos;
+  score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);
+  Ctx* C = a.ctxs + ctx;
+  for (int s = threadIdx.x; s < 3 * a.bw; s += blockDim.x) C->slots[s] = s;
+  char* seed = slot_ptr(a, ctx, 0);
+  store_msg(g, L, (float*)seed);
+  store_bits<CPT>(g, (uint32_t*)(slot_ptr(a, ctx, 3 * a.bw) + slot_ehat_off(g)), rg.ebits);
+  if (threadIdx.x == 0) {
+    *(int32_t*)(seed + slot_pairs_off(g)) = 0;
+    C->shot = (int32_t)shot;
+    C->round = 1;
+    C->nset = 1;
+    C->pending = 2;
+    C->best_gen = 0x7FFFFFFF;
+    C->nresults = 0;
+    C->t_start = t0;
+    C->parent_next_pos[0] = next_pos;
+    __hip_atomic_fetch_add(&a.st->deep, 1ull, __ATOMIC_RELAXED, AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 0u);
+    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 1u);
+  }
+  return true;
+}
+
+template <int CPT, int PW>
+__device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& L,
+                                              const Res<CPT, PW>& R, uint32_t item,
+                                              unsigned long long& nruns,
+                                              unsigned long long& niters) {
+  const DevGraph& g = a.g;
+  const int ctx = (int)(item >> 8), c = (int)(item & 255u);
+  Ctx* C = a.ctxs + ctx;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    __threadfence();
+    L.misc[10] = C->nset;
+    L.misc[11] = C->slots[c >> 1];
+    L.misc[12] = C->slots[C->nset + c];
+    L.misc[13] = C->parent_next_pos[c >> 1];
+    L.misc[14] = C->shot;
+    L.misc[15] = __hip_atomic_load(&C->best_gen, __ATOMIC_RELAXED, AGENT) < c;
+  }
+  __syncthreads();
+  __threadfence();
+  const int ps = L.misc[11], ms = L.misc[12], npos = L.misc[13], skip = L.misc[15];
+  const long long shot = L.misc[14];
+  char* pslot = slot_ptr(a, ctx, ps);
+  char* mslot = slot_ptr(a, ctx, ms);
+  int state = 2;
+  if (!skip) {
+    const int np = *(const int32_t*)(pslot + slot_pairs_off(g));
+    const int32_t* pp = (const int32_t*)(pslot + slot_pairs_off(g) + 16);
+    int32_t* mp = (int32_t*)(mslot + slot_pairs_off(g) + 16);
+    for (int q = tid; q <= np; q += blockDim.x) {
+      const int32_t v = q < np ? pp[q] : ((npos << 1) | (c & 1));
+      L.pairs[q] = v;
+      mp[q] = v;
+    }
+    if (tid == 0) *(int32_t*)(mslot + slot_pairs_off(g)) = np + 1;
+    __syncthreads();
+    RunRegs<CPT> rg;
+    const RunRes rr = bp_run<CPT, PW>(g, L, R, (const float*)pslot, nullptr, np + 1,
+                                      a.syn + shot * g.m, a.round_iters, true, a.alpha,
+                                      &C->best_gen, c, rg, &a.st->error);
+    nruns += 1;
+    niters += rr.iters;
+    uint32_t* mbitsv = (uint32_t*)(mslot + slot_ehat_off(g));
+    if (rr.cancelled) {
+      state = 2;
+    } else if (rr.conv) {
+      state = 1;
+      store_bits<CPT>(g, mbitsv, (rg.ebits & ~rg.mbits) | rg.vbits);
+      if (tid == 0) __hip_atomic_fetch_min(&C->best_gen, c, __ATOMIC_RELAXED, AGENT);
+    } else {
+      state = 0;
+      float score;
+      int next_pos;
+      score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);
+      store_msg(g, L, (float*)mslot);
+      store_bits<CPT>(g, mbitsv, (rg.ebits & ~rg.mbits) | rg.vbits);
+      if (tid == 0) {
+        C->child_score[c] = score;
+        C->child_next_pos[c] = next_pos;
+      }
+    }
+  }
+  if (tid == 0) C->child_state[c] = state;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const int left = __hip_atomic_fetch_add(&C->pending, -1, __ATOMIC_ACQ_REL, AGENT);
+    L.misc[16] = (left == 1);
+  }
+  __syncthreads();
+  const int last = L.misc[16];
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    select_round(a, L, ctx);
+  }
+}
+
+// Persistent batched decoder.  Each workgroup holds one spare context for
+// the shot whose initial run fails; it claims shots in chunks and prefers
+// queued child runs of shots already in the beam.
+template <int CPT, int PW>
+__global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const LdsMap L = lds_map(a.g, lds_raw);
+  Res<CPT, PW> R;
+  load_res<CPT, PW>(a.g, L, R);
+  unsigned long long nruns = 0, niters = 0;
+  const int tid = threadIdx.x;
+  constexpr int kChunk = 8;
+  int spare = -1;                 // thread 0 only
+  long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
+  for (;;) {
+    if (tid == 0) {
+      int kind = 0;
+      uint32_t item = 0;
+      long long shot = -1;
+      if (ring_pop(&a.st->work, a.work_ring, &item)) {
+        kind = 1;
+      } else {
+        if (spare < 0) {
+          uint32_t cx;
+          if (ring_pop(&a.st->ctxq, a.ctx_ring, &cx)) spare = (int)cx;
+        }
+        if (spare >= 0) {
+          if (cnext >= cend) {
+            const unsigned long long b = __hip_atomic_fetch_add(
+                &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
+            cnext = (long long)b;
+            cend = (long long)b + kChunk < a.shots ? (long long)b + kChunk : a.shots;
+          }
+          if (cnext < cend) {
+            kind = 2;
+            shot = cnext++;
+            item = (uint32_t)spare;
+          }
+        }
+      }
+      if (kind == 0) {
+        if (__hip_atomic_load(&a.st->done, __ATOMIC_ACQUIRE, AGENT) >= (unsigned long long)a.shots)
+          kind = 3;
+        else
+          __builtin_amdgcn_s_sleep(8);
+      }
+      L.misc[20] = kind;
+      L.misc[21] = (int)item;
+      L.misc[22] = (int)(shot & 0xFFFFFFFF);
+      L.misc[23] = (int)(shot >> 32);
+    }
+    __syncthreads();
+    const int kind = L.misc[20];
+    const uint32_t item = (uint32_t)L.misc[21];
+    const long long shot = (long long)(uint32_t)L.misc[22] | ((long long)L.misc[23] << 32);
+    __syncthreads();
+    if (kind == 3) break;
+    if (kind == 2) {
+      if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters) && tid == 0) spare = -1;
+    } else if (kind == 1) {
+      process_child<CPT, PW>(a, L, R, item, nruns, niters);
+    }
+  }
+  if (tid == 0) {
+    __hip_atomic_fetch_add(&a.st->runs, nruns, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->iterations, niters, __ATOMIC_RELAXED, AGENT);
+  }
+}
+
+// A single BP run launched on its own (grid of one workgroup).
+template <int CPT, int PW>
+__global__ void __launch_bounds__(1024) k_single(SingleArgs a) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const DevGraph& g = a.g;
+  const LdsMap L = lds_map(g, lds_raw);
+  Res<CPT, PW> R;
+  load_res<CPT, PW>(g, L, R);
+  const int tid = threadIdx.x, B = blockDim.x;
+  for (int q = tid; q < a.npairs; q += B) L.pairs[q] = a.pairs[q];
+  __syncthreads();
+  RunRegs<CPT> rg;
+  const RunRes rr = bp_run<CPT, PW>(g, L, R, a.parent, a.parent_csc, a.npairs, a.syn, a.max_iters,
+                                    a.stop != 0, a.alpha, nullptr, 0, rg, a.error);
+  float score = 0.f;
+  int next_pos = -1;
+  if (a.want_score) score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);
+  if (a.out_msg && !rr.conv) store_msg(g, L, a.out_msg);
+  const uint32_t filled = (rg.ebits & ~rg.mbits) | rg.vbits;
+  if (a.out_ehat_bits) store_bits<CPT>(g, a.out_ehat_bits, filled);
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + tid;
+    if (j >= g.n) continue;
+    const bool mk = (rg.mbits >> c) & 1u;
+    if (a.out_sumllr) a.out_sumllr[j] = mk ? 0.f : rg.sumllr[c];
+    if (a.out_ehat)
+      a.out_ehat[j] = (uint8_t)(((rr.conv ? filled : (rg.ebits & ~rg.mbits)) >> c) & 1u);
+    if (a.out_csc) {
+      const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
+      for (int e = 0; e < dg; ++e) a.out_csc[st + e] = L.msg[g.cedge[st + e] & 0xFFFFu];
+    }
+  }
+  if (tid == 0) {
+    a.result[0] = rr.iters;
+    a.result[1] = rr.conv;
+    a.result[2] = next_pos;
+    a.result[3] = __float_as_int(score);
+  }
+}
+
+}  // namespace dev
+
+// Per-PW entry points (defined in bsd_kernels_pw<PW>.hip).
+template <int PW>
+hipError_t launch_single_pw(const SingleArgs& a, int block, int cpt, size_t lds, hipStream_t s);
+template <int PW>
+hipError_t launch_batched_pw(const BatchArgs& a, int grid, int block, int cpt, size_t lds,
+                             hipStream_t s);
+template <int PW>
+hipError_t limits_pw(int cpt, size_t lds);
+template <int PW>
+hipError_t occupancy_pw(int cpt, int block, size_t lds, int* n);
+
+#define BSD_DECLARE_PW(P)                                                                        \
+  template <> hipError_t launch_single_pw<P>(const SingleArgs&, int, int, size_t, hipStream_t);  \
+  template <> hipError_t launch_batched_pw<P>(const BatchArgs&, int, int, int, size_t,           \
+                                              hipStream_t);                                      \
+  template <> hipError_t limits_pw<P>(int, size_t);                                              \
+  template <> hipError_t occupancy_pw<P>(int, int, size_t, int*);
+BSD_DECLARE_PW(1)
+BSD_DECLARE_PW(2)
+BSD_DECLARE_PW(3)
+BSD_DECLARE_PW(4)
+#undef BSD_DECLARE_PW
+
+}  // namespace bsd
+
+// Instantiates the per-PW entry points for CPT = 1..16 (used by bsd_kernels_pw<PW>.hip).
+#define BSD_DEFINE_PW(PWV)                                                                       \
+  namespace bsd {                                                                                \
+  namespace {                                                                                    \
+  template <int CPT>                                                                             \
+  hipError_t ls_(const SingleArgs& a, int block, size_t lds, hipStream_t s) {                    \
+    hipLaunchKernelGGL((dev::k_single<CPT, PWV>), dim3(1), dim3(block), lds, s, a);              \
+    return hipGetLastError();                                                                    \
+  }                                                                                              \
+  template <int CPT>                                                                             \
+  hipError_t lb_(const BatchArgs& a, int grid, int block, size_t lds, hipStream_t s) {           \
+    hipLaunchKernelGGL((dev::k_batched<CPT, PWV>), dim3(grid), dim3(block), lds, s, a);          \
+    return hipGetLastError();                                                                    \
+  }                                                                                              \
+  template <int CPT>                                                                             \
+  hipError_t lim_(size_t lds) {                                                                  \
+    hipError_t e = hipFuncSetAttribute((const void*)dev::k_single<CPT, PWV>,                     \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    if (e != hipSuccess) return e;                                                               \
+    return hipFuncSetAttribute((const void*)dev::k_batched<CPT, PWV>,                            \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+  }                                                                                              \
+  template <int CPT>                                                                             \
+  hipError_t occ_(int block, size_t lds, int* n) {                                               \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, dev::k_batched<CPT, PWV>, block, lds); \
+  }                                                                                              \
+  }                                                                                              \
+  template <>                                                                                    \
+  hipError_t launch_single_pw<PWV>(const SingleArgs& a, int block, int cpt, size_t lds,          \
+                                   hipStream_t s) {                                              \
+    BSD_CPT_SWITCH(cpt, ls_, (a, block, lds, s))                                                 \
+  }                                                                                              \
+  template <>                                                                                    \
+  hipError_t launch_batched_pw<PWV>(const BatchArgs& a, int grid, int block, int cpt,            \
+                                    size_t lds, hipStream_t s) {                                 \
+    BSD_CPT_SWITCH(cpt, lb_, (a, grid, block, lds, s))                                           \
+  }                                                                                              \
+  template <>                                                                                    \
+  hipError_t limits_pw<PWV>(int cpt, size_t lds) { BSD_CPT_SWITCH(cpt, lim_, (lds)) }            \
+  template <>                                                                                    \
+  hipError_t occupancy_pw<PWV>(int cpt, int block, size_t lds, int* n) {                         \
+    BSD_CPT_SWITCH(cpt, occ_, (block, lds, n))                                                   \
+  }                                                                                              \
+  }
+
+#define BSD_CPT_SWITCH(cpt, F, ARGS)            \
+  switch (cpt) {                                \
+    case 1: return F<1> ARGS;                   \
+    case 2: return F<2> ARGS;                   \
+    case 3: return F<3> ARGS;                   \
+    case 4: return F<4> ARGS;                   \
+    case 5: return F<5> ARGS;                   \
+    case 6: return F<6> ARGS;                   \
+    case 7: return F<7> ARGS;                   \
+    case 8: return F<8> ARGS;                   \
+    case 9: return F<9> ARGS;                   \
+    case 10: return F<10> ARGS;                 \
+    case 11: return F<11> ARGS;                 \
+    case 12: return F<12> ARGS;                 \
+    case 13: return F<13> ARGS;                 \
+    case 14: return F<14> ARGS;                 \
+    case 15: return F<15> ARGS;                 \
+    case 16: return F<16> ARGS;                 \
+    default: return hipErrorInvalidValue;       \
+  }

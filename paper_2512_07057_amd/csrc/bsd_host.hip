@@ -65,7 +65,7 @@ uint32_t pow2_at_least(uint64_t x) {
 struct bsd_code_s {
   int device = 0;
   DevGraph g{};
-  int block = 64, cpt = 1, grid = 1;
+  int block = 64, cpt = 1, pw = 1, grid = 1;
   size_t lds = 0;
   std::vector<void*> owned;  // device buffers of the graph
   std::vector<int32_t> colptr, rowidx;
@@ -205,7 +205,7 @@ bsd_status plain_run(bsd_code c, hipStream_t s, const float* parent, const std::
   a.out_ehat_bits = out_bits;
   a.result = c->d_result;
   a.error = c->d_error;
-  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->lds, s));
+  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->pw, c->lds, s));
   int32_t* res = c->h_pinned + kMaxRounds;
   HIP_OR_FAIL(hipMemcpyAsync(res, c->d_result, 16, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -365,7 +365,7 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.slots_per_ctx = 3 * c->ws_bw + 1;
   HIP_OR_FAIL(launch_batch_reset(a, s));
   HIP_OR_FAIL(hipEventRecord(c->ev0, s));
-  HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->lds, s));
+  HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
   HIP_OR_FAIL(hipEventRecord(c->ev1, s));
   HIP_OR_FAIL(hipMemcpyAsync(c->st_host, c->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -503,31 +503,36 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   g.lambda = d_lam;
   g.lmask = d_lm;
 
-  // Launch geometry: one BP run per workgroup; columns c * block + tid.
-  c->lds = lds_bytes_for(g, 0, 0);
+  // Launch geometry: one BP run per workgroup; columns c * block + tid,
+  // detector rows of rank q * block + tid (q < 2).
+  c->lds = lds_bytes_for(g);
   if (c->lds > (size_t)kLdsBytes || nnz > 65535) {
     bsd_code_destroy(c);
     return fail(BSD_EINVAL, "graph too large: %d edges need %zu bytes of LDS (limit %d)", nnz,
                 c->lds, kLdsBytes);
   }
+  int maxdeg_col = 1;
+  for (int j = 0; j < n; ++j) maxdeg_col = std::max(maxdeg_col, h_colptr[j + 1] - h_colptr[j]);
+  c->pw = (maxdeg_col + 1) / 2;
   if (c->lds > 64 * 1024) {
     c->block = 1024;
   } else {
     c->block = 64;
-    while ((n + c->block - 1) / c->block > kMaxCpt) c->block *= 2;
+    while ((n + c->block - 1) / c->block > kMaxCpt || m > 2 * c->block) c->block *= 2;
   }
   c->cpt = (n + c->block - 1) / c->block;
-  if (c->cpt > kMaxCpt) {
+  if (c->block > 1024 || c->cpt > kMaxCpt || m > 2 * c->block) {
     bsd_code_destroy(c);
-    return fail(BSD_EINVAL, "n = %d too large (limit %d)", n, kMaxCpt * 1024);
+    return fail(BSD_EINVAL, "graph too large: n = %d (limit %d), m = %d (limit 2048)", n,
+                kMaxCpt * 1024, m);
   }
-  hipError_t he = set_kernel_limits(c->cpt, c->lds);
+  hipError_t he = set_kernel_limits(c->cpt, c->pw, c->lds);
   if (he != hipSuccess) {
     bsd_code_destroy(c);
     return fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
   }
   int per_cu = 0, ncu = 0;
-  he = batched_occupancy(c->cpt, c->block, c->lds, &per_cu);
+  he = batched_occupancy(c->cpt, c->pw, c->block, c->lds, &per_cu);
   if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (he != hipSuccess || per_cu < 1) {
     bsd_code_destroy(c);
@@ -641,7 +646,7 @@ bsd_status bsd_bp_run(bsd_code c, const float* e_start, const int32_t* pairs, in
   a.out_ehat = ehat;
   a.result = c->d_result;
   a.error = c->d_error;
-  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->lds, s));
+  HIP_OR_FAIL(launch_single(a, c->block, c->cpt, c->pw, c->lds, s));
   int32_t* res = c->h_pinned + kMaxRounds;
   HIP_OR_FAIL(hipMemcpyAsync(res, c->d_result, 16, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipMemcpyAsync(res + 4, c->d_error, 4, hipMemcpyDeviceToHost, s));

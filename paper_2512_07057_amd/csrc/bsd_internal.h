@@ -147,15 +147,17 @@ struct EmitArgs {
   int32_t converged;
 };
 
-// Host-side launchers implemented in bsd_kernels.hip.
-hipError_t launch_single(const SingleArgs& a, int block, int cpt, size_t lds, hipStream_t s);
-hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, size_t lds,
+// Host-side launchers (bsd_kernels_common.hip).  pw = words of 16-bit edge
+// positions per column kept in registers = ceil(largest column degree / 2).
+hipError_t launch_single(const SingleArgs& a, int block, int cpt, int pw, size_t lds,
+                         hipStream_t s);
+hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, int pw, size_t lds,
                           hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
-hipError_t set_kernel_limits(int cpt, size_t lds);
-hipError_t batched_occupancy(int cpt, int block, size_t lds, int* blocks_per_cu);
+hipError_t set_kernel_limits(int cpt, int pw, size_t lds);
+hipError_t batched_occupancy(int cpt, int pw, int block, size_t lds, int* blocks_per_cu);
 
-size_t lds_bytes_for(const DevGraph& g, int block, int cpt);
+size_t lds_bytes_for(const DevGraph& g);
 
 }  // namespace bsd
