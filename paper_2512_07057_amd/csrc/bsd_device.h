@@ -12,6 +12,10 @@
 // registers, so a run touches only LDS apart from its syndrome, its
 // warm-start messages and its results.
 //
+// LDS layout: a fixed 7072-byte area of small arrays at offset 0 (constant
+// offsets), then the messages, then one trash word per lane that absorbs
+// stores of absent edges so the inner loops need no branches.
+//
 // Floating-point order follows the paper's formulas left to right: sums run
 // over neighbours in ascending row index, E of eq. (2) is a literal exclusive
 // sum (the shared prefix is reused, the skipped term is never added and
@@ -29,67 +33,40 @@ constexpr int AGENT = __HIP_MEMORY_SCOPE_AGENT;
 constexpr uint32_t kInfBits = 0x7F800000u;
 constexpr uint32_t kSignBit = 0x80000000u;
 
-struct LdsMap {
-  float* msg;
-  int32_t* diag;     // [maxdeg_row + 1] jagged-diagonal starts
-  uint32_t* sprime;  // masked syndrome s' by row rank
-  uint32_t* resid;   // s' xor H e-hat
-  int32_t* pairs;    // packed (col << 1) | val
-  float* redf;       // [kMaxCpt][kMaxWaves] score partials
-  float* aminv;      // [kMaxWaves]
-  int32_t* aminj;    // [kMaxWaves]
-  uint32_t* flw;     // [2 * kMaxWaves] logical flip partials
-  int32_t* misc;     // [32]
-  int32_t* order;    // [2 * kMaxBw] rank of each child
-  int32_t* byrank;   // [2 * kMaxBw] child of each rank
-  int32_t* mark;     // [3 * kMaxBw + 1]
-  int32_t* newslots; // [3 * kMaxBw]
-  float* part;       // [kMaxCpt]
+// Fixed LDS offsets (bytes).
+constexpr int kMaxWordsM = 64;                       // m <= 2048
+constexpr int kOffDiag = 0;                          // int32[256] jagged-diagonal starts
+constexpr int kOffSprime = kOffDiag + 1024;          // uint32[64] s' by row rank
+constexpr int kOffResid = kOffSprime + 256;          // uint32[2][64] s' xor H e-hat
+constexpr int kOffPairs = kOffResid + 512;           // int32[64] packed (col << 1) | val
+constexpr int kOffMisc = kOffPairs + 256;            // int32[32]
+constexpr int kOffFlips = kOffMisc + 128;            // uint32[4] logical-flip accumulator
+constexpr int kOffRedf = kOffFlips + 16;             // float[32][16] score partials
+constexpr int kOffPart = kOffRedf + 2048;            // float[32]
+constexpr int kOffAminv = kOffPart + 128;            // float[16]
+constexpr int kOffAminj = kOffAminv + 64;            // int32[16]
+constexpr int kOffOrder = kOffAminj + 64;            // int32[128] rank of each child
+constexpr int kOffByrank = kOffOrder + 512;          // int32[128] child of each rank
+constexpr int kOffMark = kOffByrank + 512;           // int32[196]
+constexpr int kOffNewslots = kOffMark + 784;         // int32[192]
+constexpr int kOffMsg = kOffNewslots + 768;          // float[nnz_pad + 64]
+static_assert(kOffMsg % 16 == 0, "message area must be 16-byte aligned");
+
+struct Lds {
+  char* base;
+  __device__ __forceinline__ uint32_t* u32(int off) const { return reinterpret_cast<uint32_t*>(base + off); }
+  __device__ __forceinline__ int32_t* i32(int off) const { return reinterpret_cast<int32_t*>(base + off); }
+  __device__ __forceinline__ float* f32(int off) const { return reinterpret_cast<float*>(base + off); }
+  __device__ __forceinline__ float* msg() const { return f32(kOffMsg); }
+  __device__ __forceinline__ uint32_t* msgu() const { return u32(kOffMsg); }
+  __device__ __forceinline__ int32_t* misc() const { return i32(kOffMisc); }
+  __device__ __forceinline__ int32_t* pairs() const { return i32(kOffPairs); }
+  __device__ __forceinline__ uint32_t* sprime() const { return u32(kOffSprime); }
+  __device__ __forceinline__ uint32_t* resid(int b) const { return u32(kOffResid + 256 * b); }
 };
 
-__host__ __device__ inline size_t diag_words(const DevGraph& g) {
-  return ((size_t)g.maxdeg_row + 1 + 3) & ~(size_t)3;
-}
-
-__host__ __device__ inline size_t lds_tail_bytes(const DevGraph& g) {
-  return diag_words(g) * 4 + (size_t)g.words_m * 8 + kMaxRounds * 4 + kMaxCpt * kMaxWaves * 4 +
-         kMaxWaves * 8 + 2 * kMaxWaves * 4 + 32 * 4 + 4 * kMaxBw * 4 + (3 * kMaxBw + 1) * 4 +
-         3 * kMaxBw * 4 + kMaxCpt * 4;
-}
-
-__device__ __forceinline__ LdsMap lds_map(const DevGraph& g, char* lds) {
-  LdsMap L;
-  char* p = lds;
-  L.msg = (float*)p;
-  p += (size_t)g.nnz_pad * 4;
-  L.diag = (int32_t*)p;
-  p += diag_words(g) * 4;
-  L.sprime = (uint32_t*)p;
-  p += (size_t)g.words_m * 4;
-  L.resid = (uint32_t*)p;
-  p += (size_t)g.words_m * 4;
-  L.pairs = (int32_t*)p;
-  p += kMaxRounds * 4;
-  L.redf = (float*)p;
-  p += kMaxCpt * kMaxWaves * 4;
-  L.aminv = (float*)p;
-  p += kMaxWaves * 4;
-  L.aminj = (int32_t*)p;
-  p += kMaxWaves * 4;
-  L.flw = (uint32_t*)p;
-  p += 2 * kMaxWaves * 4;
-  L.misc = (int32_t*)p;
-  p += 32 * 4;
-  L.order = (int32_t*)p;
-  p += 2 * kMaxBw * 4;
-  L.byrank = (int32_t*)p;
-  p += 2 * kMaxBw * 4;
-  L.mark = (int32_t*)p;
-  p += (3 * kMaxBw + 1) * 4;
-  L.newslots = (int32_t*)p;
-  p += 3 * kMaxBw * 4;
-  L.part = (float*)p;
-  return L;
+__host__ __device__ inline size_t lds_need(const DevGraph& g) {
+  return (size_t)kOffMsg + ((size_t)g.nnz_pad + 64) * 4;
 }
 
 // Graph data of one lane, read once per launch.  Lane tid owns columns
@@ -97,11 +74,28 @@ __device__ __forceinline__ LdsMap lds_map(const DevGraph& g, char* lds) {
 template <int CPT, int PW>
 struct Res {
   float lam[CPT];
-  uint32_t pos[CPT][PW];          // LDS positions of the column's edges, 16 bits each, CSC order
+  uint32_t pos[CPT][PW];          // LDS positions of the column's edges (16 bits each, CSC
+                                  // order); absent edges point at the lane's trash word
   uint32_t deg[(CPT + 7) / 8];    // 4 bits per column
   uint32_t dmx[(CPT + 7) / 8];    // 4 bits per column: largest degree in the wave
-  uint32_t row[2];                // original row (16 bits) | degree << 16; 0xFFFFFFFF past m
+  uint32_t row[2];                // original row (bits 0..15) | degree << 16 | 1 << 31; 0 past m
 };
+
+// Hide a lane's graph registers from loop-invariant code motion, so that
+// values derived from them are recomputed where used instead of being kept
+// live (unpacked) across runs.
+template <int CPT, int PW>
+__device__ __forceinline__ void opaque_res(Res<CPT, PW>& R) {
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+    for (int w = 0; w < PW; ++w) asm volatile("" : "+v"(R.pos[c][w]));
+    asm volatile("" : "+v"(R.lam[c]));
+  }
+#pragma unroll
+  for (int w = 0; w < (CPT + 7) / 8; ++w) asm volatile("" : "+v"(R.deg[w]), "+v"(R.dmx[w]));
+  asm volatile("" : "+v"(R.row[0]), "+v"(R.row[1]));
+}
 
 template <int CPT>
 struct RunRegs {
@@ -110,6 +104,10 @@ struct RunRegs {
   uint32_t mbits;  // masked columns
   uint32_t vbits;  // values of masked columns
 };
+
+// Largest workgroup a kernel instance is compiled for: lanes that own more
+// than 9 columns get a 256-register budget (at most 512 threads).
+constexpr int max_block_for(int cpt) { return cpt > 9 ? 512 : 1024; }
 
 struct RunRes {
   int iters;
@@ -138,11 +136,16 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t trash_pos(const DevGraph& g) {
+  return (uint32_t)g.nnz_pad + (threadIdx.x & 63u);
+}
+
 // Load a lane's graph data (called by every thread, before any run).
 template <int CPT, int PW>
-__device__ __forceinline__ void load_res(const DevGraph& g, const LdsMap& L, Res<CPT, PW>& R) {
+__device__ __forceinline__ void load_res(const DevGraph& g, const Lds& L, Res<CPT, PW>& R) {
   const int tid = threadIdx.x, B = blockDim.x;
-  for (int i = tid; i <= g.maxdeg_row; i += B) L.diag[i] = g.diag_ptr[i];
+  for (int i = tid; i < 256; i += B) L.i32(kOffDiag)[i] = i <= g.maxdeg_row ? g.diag_ptr[i] : 0;
+  const uint32_t tp = trash_pos(g);
 #pragma unroll
   for (int w = 0; w < (CPT + 7) / 8; ++w) R.deg[w] = R.dmx[w] = 0u;
 #pragma unroll
@@ -150,16 +153,18 @@ __device__ __forceinline__ void load_res(const DevGraph& g, const LdsMap& L, Res
     const int j = c * B + tid;
     int dg = 0;
     R.lam[c] = 0.f;
-#pragma unroll
-    for (int w = 0; w < PW; ++w) R.pos[c][w] = 0u;
+    int st = 0;
     if (j < g.n) {
       const uint32_t info = g.colinfo[j];
-      const int st = (int)(info & 0xFFFFFFu);
+      st = (int)(info & 0xFFFFFFu);
       dg = (int)(info >> 24);
       R.lam[c] = g.lambda[j];
+    }
 #pragma unroll
-      for (int e = 0; e < 2 * PW; ++e)
-        if (e < dg) R.pos[c][e >> 1] |= (g.cedge[st + e] & 0xFFFFu) << (16 * (e & 1));
+    for (int w = 0; w < PW; ++w) {
+      const uint32_t p0 = 2 * w < dg ? (g.cedge[st + 2 * w] & 0xFFFFu) : tp;
+      const uint32_t p1 = 2 * w + 1 < dg ? (g.cedge[st + 2 * w + 1] & 0xFFFFu) : tp;
+      R.pos[c][w] = p0 | (p1 << 16);
     }
     R.deg[c >> 3] |= (uint32_t)dg << (4 * (c & 7));
     R.dmx[c >> 3] |= (uint32_t)wave_max_i(dg) << (4 * (c & 7));
@@ -167,79 +172,129 @@ __device__ __forceinline__ void load_res(const DevGraph& g, const LdsMap& L, Res
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int r = q * B + tid;
-    R.row[q] = r < g.m ? ((uint32_t)g.row_of_rank[r] | ((uint32_t)g.deg_of_rank[r] << 16))
-                       : 0xFFFFFFFFu;
+    R.row[q] = r < g.m ? ((uint32_t)g.row_of_rank[r] | ((uint32_t)g.deg_of_rank[r] << 16) | kSignBit)
+                       : 0u;
   }
   __syncthreads();
 }
 
-// Eq. (1) for the detector row of rank r, in place: E(t-1) -> D(t) on the
-// unmasked edges (masked edges hold +inf and are skipped).  Magnitudes of
-// non-negative floats compare as unsigned integers.
-__device__ __forceinline__ void check_row(const LdsMap& L, int r, int dg, float alpha) {
-  uint32_t* msg = reinterpret_cast<uint32_t*>(L.msg);
-  const int kmax = __builtin_amdgcn_readfirstlane(dg);  // ranks are sorted by degree
-  uint32_t sgn = ((L.sprime[r >> 5] >> (r & 31)) & 1u) << 31;
+// Eq. (1) for the detector rows of rank q * B + tid, in place: E(t-1) -> D(t)
+// on the unmasked edges (masked edges hold +inf and are skipped).  Magnitudes
+// of non-negative floats compare as unsigned integers.  Ranks are sorted by
+// degree, so in a wave every row has at least the last lane's degree and at
+// most the first lane's: that range is the only part that needs predicates.
+__device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint32_t rowinfo, int r,
+                                           float alpha) {
+  uint32_t* msg = L.msgu();
+  const int32_t* diag = L.i32(kOffDiag);
+  asm volatile("" : "+v"(rowinfo));
+  const int dg = (int)((rowinfo >> 16) & 0xFFu);
+  const int kmax = __builtin_amdgcn_readfirstlane(dg);
+  if (kmax == 0) return;
+  const int kmin = __builtin_amdgcn_readlane(dg, 63);
+  const uint32_t tp = trash_pos(g);
+  uint32_t sgn = dg ? ((L.sprime()[r >> 5] >> (r & 31)) & 1u) << 31 : 0u;
   uint32_t m1 = __float_as_uint(kLlrMax), m2 = m1;
   int arg = -1;
-  for (int k = 0; k < kmax; ++k) {
-    const int p = L.diag[k] + r;
-    if (k < dg) {
-      const uint32_t v = msg[p];
-      const uint32_t a = v & ~kSignBit;
-      sgn ^= v;
+  int k = 0;
+  for (; k + 4 <= kmin; k += 4) {
+    const int4 dd = *reinterpret_cast<const int4*>(diag + k);
+    const uint32_t v0 = msg[dd.x + r], v1 = msg[dd.y + r], v2 = msg[dd.z + r], v3 = msg[dd.w + r];
+    const uint32_t vv[4] = {v0, v1, v2, v3};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t a = vv[u] & ~kSignBit;
+      sgn ^= vv[u];
       m2 = min(m2, max(m1, a));
-      arg = a < m1 ? k : arg;
+      arg = a < m1 ? k + u : arg;
       m1 = min(m1, a);
     }
   }
+  for (; k < kmax; ++k) {
+    const bool ok = k < dg;
+    const uint32_t v = msg[ok ? (uint32_t)(diag[k] + r) : tp];
+    const uint32_t a = ok ? (v & ~kSignBit) : kInfBits;
+    sgn ^= ok ? v : 0u;
+    m2 = min(m2, max(m1, a));
+    arg = a < m1 ? k : arg;
+    m1 = min(m1, a);
+  }
   const uint32_t d1 = __float_as_uint(fminf(alpha * __uint_as_float(m1), kLlrMax));
   const uint32_t d2 = __float_as_uint(fminf(alpha * __uint_as_float(m2), kLlrMax));
-  for (int k = 0; k < kmax; ++k) {
-    const int p = L.diag[k] + r;
-    if (k < dg) {
-      const uint32_t v = msg[p];
-      if (v != kInfBits) msg[p] = (k == arg ? d2 : d1) | ((sgn ^ v) & kSignBit);
+  k = 0;
+  for (; k + 4 <= kmin; k += 4) {
+    const int4 dd = *reinterpret_cast<const int4*>(diag + k);
+    const int pp[4] = {dd.x + r, dd.y + r, dd.z + r, dd.w + r};
+    uint32_t vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vv[u] = msg[pp[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t d = (k + u == arg ? d2 : d1) | ((sgn ^ vv[u]) & kSignBit);
+      msg[pp[u]] = vv[u] == kInfBits ? vv[u] : d;
     }
+  }
+  for (; k < kmax; ++k) {
+    const bool ok = k < dg;
+    const uint32_t p = ok ? (uint32_t)(diag[k] + r) : tp;
+    const uint32_t v = msg[p];
+    const uint32_t d = (k == arg ? d2 : d1) | ((sgn ^ v) & kSignBit);
+    msg[p] = v == kInfBits ? v : d;
   }
 }
 
 // Eqs. (2)-(4) for one column with at most D edges (D uniform over the wave).
 template <int D, int CPT, int PW>
-__device__ __forceinline__ void var_col(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
-                                        int c, bool active, float& sl, uint32_t& eb) {
-  const int dg = col_deg(R, c);
+__device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_t* resid,
+                                        const Res<CPT, PW>& R, int c, bool active, float& sl,
+                                        uint32_t& eb) {
+  float* msg = L.msg();
+  uint32_t dw = R.deg[c >> 3];
+  asm volatile("" : "+v"(dw));
+  const int dg = (int)((dw >> (4 * (c & 7))) & 15u);
+  const uint32_t tp = trash_pos(g);
+  uint32_t p[D];
   float d[D];
+  // Unpack the positions here, inside the iteration: kept packed across
+  // iterations they cost half the registers.
+  uint32_t pk[PW];
 #pragma unroll
-  for (int e = 0; e < D; ++e) d[e] = (active && e < dg) ? L.msg[col_pos(R, c, e)] : 0.f;
-  if (!active) return;
-  float pre = R.lam[c];
+  for (int w = 0; w < PW; ++w) {
+    pk[w] = R.pos[c][w];
+    asm volatile("" : "+v"(pk[w]));
+  }
 #pragma unroll
   for (int e = 0; e < D; ++e) {
-    if (e < dg) {  // eq. (2): the prefix before e, then the terms after e
-      float x = pre;
+    p[e] = (pk[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    const float x = msg[p[e]];
+    d[e] = e < dg ? x : 0.f;
+    p[e] = active ? p[e] : tp;
+  }
+  float pre = R.lam[c];
 #pragma unroll
-      for (int f = e + 1; f < D; ++f) x = x + d[f];
-      L.msg[col_pos(R, c, e)] = fminf(fmaxf(x, -kLlrMax), kLlrMax);
-    }
+  for (int e = 0; e < D; ++e) {  // eq. (2): the prefix before e, then the terms after e
+    float x = pre;
+#pragma unroll
+    for (int f = e + 1; f < D; ++f) x = x + d[f];
+    msg[p[e]] = fminf(fmaxf(x, -kLlrMax), kLlrMax);
     pre = pre + d[e];
   }
   const float post = pre;  // eq. (3)
-  sl = sl + post;
-  eb = post <= 0.f ? 1u : 0u;  // eq. (4)
+  sl = active ? sl + post : sl;
+  eb = (active && post <= 0.f) ? 1u : 0u;  // eq. (4)
   if (eb) {
     const int j = c * (int)blockDim.x + (int)threadIdx.x;
     const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
     for (int e = 0; e < dg; ++e) {
       const uint32_t rk = g.cedge[st + e] >> 16;
-      atomicXor(&L.resid[rk >> 5], 1u << (rk & 31));
+      atomicXor(&resid[rk >> 5], 1u << (rk & 31));
     }
   }
 }
 
 template <int CPT, int PW>
-__device__ __forceinline__ void var_phase(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
-                                          RunRegs<CPT>& rg) {
+__device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint32_t* resid,
+                                          const Res<CPT, PW>& R, RunRegs<CPT>& rg) {
   const int B = blockDim.x;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -247,49 +302,48 @@ __device__ __forceinline__ void var_phase(const DevGraph& g, const LdsMap& L, co
     const bool active = j < g.n && !((rg.mbits >> c) & 1u);
     uint32_t eb = 0;
     const int D = col_dmax(R, c);
-    if (D == 1) var_col<1>(g, L, R, c, active, rg.sumllr[c], eb);
-    else if (D == 2) var_col<2>(g, L, R, c, active, rg.sumllr[c], eb);
-    if constexpr (PW >= 2) {
-      if (D == 3) var_col<3>(g, L, R, c, active, rg.sumllr[c], eb);
-      else if (D == 4) var_col<4>(g, L, R, c, active, rg.sumllr[c], eb);
-    }
-    if constexpr (PW >= 3) {
-      if (D == 5) var_col<5>(g, L, R, c, active, rg.sumllr[c], eb);
-      else if (D == 6) var_col<6>(g, L, R, c, active, rg.sumllr[c], eb);
-    }
-    if constexpr (PW >= 4) {
-      if (D == 7) var_col<7>(g, L, R, c, active, rg.sumllr[c], eb);
-      else if (D == 8) var_col<8>(g, L, R, c, active, rg.sumllr[c], eb);
+    switch (D) {
+      case 1: var_col<1>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 2: var_col<2>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 3: if constexpr (PW >= 2) var_col<3>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 4: if constexpr (PW >= 2) var_col<4>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 5: if constexpr (PW >= 3) var_col<5>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 6: if constexpr (PW >= 3) var_col<6>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 7: if constexpr (PW >= 4) var_col<7>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 8: if constexpr (PW >= 4) var_col<8>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      default: break;
     }
     rg.ebits = (rg.ebits & ~(1u << c)) | (eb << c);
   }
 }
 
 // One masked BP run (Algorithm 2).  The caller has placed `npairs` packed
-// pairs in L.pairs and synchronised.  Warm start from `parent` (LDS order) or
+// pairs in LDS and synchronised.  Warm start from `parent` (LDS order) or
 // `parent_csc` (CSC order), else from the priors.  When `cancel` is given the
 // run stops early once *cancel < my_gen (a lower generation converged).
 template <int CPT, int PW>
-__device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, const Res<CPT, PW>& R,
+__device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
                                          const float* parent, const float* parent_csc, int npairs,
                                          const uint8_t* syn, int T, bool stop, float alpha,
                                          const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
                                          uint32_t* err) {
   const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  float* msg = L.msg();
   rg.mbits = rg.vbits = rg.ebits = 0;
   for (int q = 0; q < npairs; ++q) {
-    const int pv = L.pairs[q];
+    const int pv = L.pairs()[q];
     const int d = (pv >> 1) - tid;
     if (d >= 0 && d % B == 0 && d / B < CPT) {
       rg.mbits |= 1u << (d / B);
       rg.vbits |= (uint32_t)(pv & 1) << (d / B);
     }
   }
+  if (tid < 4) L.u32(kOffFlips)[tid] = 0u;
   // s by row rank, 64 ranks per wave ballot.
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     uint32_t bit = 0;
-    if (R.row[q] != 0xFFFFFFFFu) {
+    if (R.row[q] >> 31) {
       const uint32_t b = syn[R.row[q] & 0xFFFFu];
       if (b > 1u) atomicOr(err, 1u);
       bit = b & 1u;
@@ -297,13 +351,13 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, con
     const unsigned long long bal = __ballot(bit);
     if (lane == 0) {
       const int w = (q * B + wave * 64) >> 5;
-      if (w < g.words_m) L.sprime[w] = (uint32_t)bal;
-      if (w + 1 < g.words_m) L.sprime[w + 1] = (uint32_t)(bal >> 32);
+      if (w < g.words_m) L.sprime()[w] = (uint32_t)bal;
+      if (w + 1 < g.words_m) L.sprime()[w + 1] = (uint32_t)(bal >> 32);
     }
   }
   if (parent) {
     const float4* src = reinterpret_cast<const float4*>(parent);
-    float4* dst = reinterpret_cast<float4*>(L.msg);
+    float4* dst = reinterpret_cast<float4*>(msg);
     for (int i = tid; i < g.nnz_pad / 4; i += B) dst[i] = src[i];
   }
 #pragma unroll
@@ -311,14 +365,12 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, con
     rg.sumllr[c] = 0.f;
     const int j = c * B + tid;
     if (!parent && j < g.n) {
-      const int dg = col_deg(R, c);
       if (parent_csc) {
-        const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
-        for (int e = 0; e < dg; ++e) L.msg[g.cedge[st + e] & 0xFFFFu] = parent_csc[st + e] + 0.f;
+        const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
+        for (int e = 0; e < dg; ++e) msg[g.cedge[st + e] & 0xFFFFu] = parent_csc[st + e] + 0.f;
       } else {
 #pragma unroll
-        for (int e = 0; e < 2 * PW; ++e)
-          if (e < dg) L.msg[col_pos(R, c, e)] = R.lam[c];
+        for (int e = 0; e < 2 * PW; ++e) msg[col_pos(R, c, e)] = R.lam[c];
       }
     }
   }
@@ -332,10 +384,10 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, con
         const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
         for (int e = 0; e < dg; ++e) {
           const uint32_t w = g.cedge[st + e];
-          L.msg[w & 0xFFFFu] = __builtin_inff();
+          msg[w & 0xFFFFu] = __builtin_inff();
           if ((rg.vbits >> c) & 1u) {
             const uint32_t rk = w >> 16;
-            atomicXor(&L.sprime[rk >> 5], 1u << (rk & 31));
+            atomicXor(&L.sprime()[rk >> 5], 1u << (rk & 31));
           }
         }
       }
@@ -345,25 +397,27 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, con
 
   RunRes rr{0, 0, 0};
   for (int t = 1; t <= T; ++t) {
-    for (int w = tid; w < g.words_m; w += B) L.resid[w] = L.sprime[w];
+    uint32_t* resid = L.resid(t & 1);
+    for (int w = tid; w < g.words_m; w += B) resid[w] = L.sprime()[w];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (R.row[q] != 0xFFFFFFFFu) check_row(L, q * B + tid, (int)(R.row[q] >> 16), alpha);
+    for (int q = 0; q < 2; ++q) check_rows(g, L, R.row[q], q * B + tid, alpha);
     __syncthreads();
-    var_phase<CPT, PW>(g, L, R, rg);
-    __syncthreads();
-    int nz = 0;
-    for (int w = tid; w < g.words_m; w += B) nz |= (L.resid[w] != 0u);
+    var_phase<CPT, PW>(g, L, resid, R, rg);
     if (tid == 0) {
       int cx = 0;
       if (cancel) cx = __hip_atomic_load(cancel, __ATOMIC_RELAXED, AGENT) < my_gen;
-      L.misc[0] = cx;
+      L.misc()[0] = cx;
     }
-    const int any = __syncthreads_or(nz);
+    __syncthreads();
+    uint32_t any = 0;
+    for (int w = 0; w < g.words_m; w += 2) {
+      const uint2 x = *reinterpret_cast<const uint2*>(resid + w);
+      any |= x.x | x.y;
+    }
     rr.iters = t;
     rr.conv = any ? 0 : 1;
     if (stop && rr.conv) break;
-    if (L.misc[0]) {
+    if (L.misc()[0]) {
       rr.cancelled = 1;
       break;
     }
@@ -375,10 +429,11 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const LdsMap& L, con
 // next_pos = least |sum_LLR| over unmasked nodes (lowest index on ties),
 // score = aligned pairwise-tree sum of |sum_LLR| over unmasked nodes / iters.
 template <int CPT>
-__device__ __forceinline__ void score_next(const DevGraph& g, const LdsMap& L,
+__device__ __forceinline__ void score_next(const DevGraph& g, const Lds& L,
                                            const RunRegs<CPT>& rg, int iters, float* score,
                                            int* next_pos) {
   const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = B >> 6;
+  float* redf = L.f32(kOffRedf);
   float bv = __builtin_inff();
   int bj = 0x7FFFFFFF;
 #pragma unroll
@@ -392,7 +447,7 @@ __device__ __forceinline__ void score_next(const DevGraph& g, const LdsMap& L,
     }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) a = a + __shfl_xor(a, o, 64);
-    if (lane == 0) L.redf[c * kMaxWaves + wave] = a;
+    if (lane == 0) redf[c * kMaxWaves + wave] = a;
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -404,39 +459,41 @@ __device__ __forceinline__ void score_next(const DevGraph& g, const LdsMap& L,
     }
   }
   if (lane == 0) {
-    L.aminv[wave] = bv;
-    L.aminj[wave] = bj;
+    L.f32(kOffAminv)[wave] = bv;
+    L.i32(kOffAminj)[wave] = bj;
   }
   __syncthreads();
   if (tid == 0) {
     // Aligned pairwise tree: over the waves of each column block, then over blocks.
+    float* part = L.f32(kOffPart);
     for (int c = 0; c < CPT; ++c) {
-      float* v = L.redf + c * kMaxWaves;
+      float* v = redf + c * kMaxWaves;
       for (int len = nw; len > 1; len >>= 1)
         for (int i = 0; i < len / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
-      L.part[c] = v[0];
+      part[c] = v[0];
     }
     int c2 = 1;
     while (c2 < CPT) c2 <<= 1;
-    for (int c = CPT; c < c2; ++c) L.part[c] = 0.f;
+    for (int c = CPT; c < c2; ++c) part[c] = 0.f;
     for (int len = c2; len > 1; len >>= 1)
-      for (int i = 0; i < len / 2; ++i) L.part[i] = L.part[2 * i] + L.part[2 * i + 1];
-    const float sc = iters > 0 ? L.part[0] / (float)iters : 0.f;
+      for (int i = 0; i < len / 2; ++i) part[i] = part[2 * i] + part[2 * i + 1];
+    const float sc = iters > 0 ? part[0] / (float)iters : 0.f;
     float mv = __builtin_inff();
     int mj = 0x7FFFFFFF;
     for (int w = 0; w < nw; ++w) {
-      if (L.aminv[w] < mv || (L.aminv[w] == mv && L.aminj[w] < mj)) {
-        mv = L.aminv[w];
-        mj = L.aminj[w];
+      const float av = L.f32(kOffAminv)[w];
+      const int aj = L.i32(kOffAminj)[w];
+      if (av < mv || (av == mv && aj < mj)) {
+        mv = av;
+        mj = aj;
       }
     }
-    L.misc[4] = __float_as_int(sc);
-    L.misc[5] = (mj == 0x7FFFFFFF) ? -1 : mj;
+    L.misc()[4] = __float_as_int(sc);
+    L.misc()[5] = (mj == 0x7FFFFFFF) ? -1 : mj;
   }
   __syncthreads();
-  *score = __int_as_float(L.misc[4]);
-  *next_pos = L.misc[5];
-  __syncthreads();
+  *score = __int_as_float(L.misc()[4]);
+  *next_pos = L.misc()[5];
 }
 
 // Hard-decision bits (one bit per column) to a global bit-vector.
@@ -455,40 +512,32 @@ __device__ __forceinline__ void store_bits(const DevGraph& g, uint32_t* dst, uin
   }
 }
 
-__device__ __forceinline__ void store_msg(const DevGraph& g, const LdsMap& L, float* dst) {
-  const float4* src = reinterpret_cast<const float4*>(L.msg);
+__device__ __forceinline__ void store_msg(const DevGraph& g, const Lds& L, float* dst) {
+  const float4* src = reinterpret_cast<const float4*>(L.msg());
   float4* d = reinterpret_cast<float4*>(dst);
   for (int i = threadIdx.x; i < g.nnz_pad / 4; i += blockDim.x) d[i] = src[i];
 }
 
-// XOR-reduce per-lane 64-bit logical flip masks over the workgroup.
-__device__ __forceinline__ unsigned long long block_xor64(const LdsMap& L, unsigned long long f) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  uint32_t lo = (uint32_t)f, hi = (uint32_t)(f >> 32);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    lo ^= __shfl_xor(lo, o, 64);
-    hi ^= __shfl_xor(hi, o, 64);
+// Logical flips A e-hat: lanes holding a 1 fold their column's mask into an
+// LDS accumulator (zeroed at the start of every run); one barrier, then the
+// bytes are written.
+__device__ __forceinline__ void flip_fold(const Lds& L, unsigned long long f) {
+  if (f) {
+    atomicXor(&L.u32(kOffFlips)[0], (uint32_t)f);
+    atomicXor(&L.u32(kOffFlips)[1], (uint32_t)(f >> 32));
   }
-  if (lane == 0) {
-    L.flw[2 * wave] = lo;
-    L.flw[2 * wave + 1] = hi;
-  }
-  __syncthreads();
-  unsigned long long t = 0;
-  for (int w = 0; w < nw; ++w)
-    t ^= (unsigned long long)L.flw[2 * w] | ((unsigned long long)L.flw[2 * w + 1] << 32);
-  __syncthreads();
-  return t;
 }
 
-__device__ __forceinline__ void write_flips(const DevGraph& g, unsigned long long t, uint8_t* flips) {
+__device__ __forceinline__ void flip_write(const DevGraph& g, const Lds& L, uint8_t* flips) {
+  __syncthreads();
+  const unsigned long long t =
+      (unsigned long long)L.u32(kOffFlips)[0] | ((unsigned long long)L.u32(kOffFlips)[1] << 32);
   for (int r = threadIdx.x; r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
 }
 
 // Shot output from register-resident hard decisions (columns c*B + tid).
 template <int CPT>
-__device__ __forceinline__ void emit_from_regs(const DevGraph& g, const LdsMap& L, uint32_t bits,
+__device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, uint32_t bits,
                                                uint8_t* corr, uint8_t* flips) {
   const int B = blockDim.x;
   unsigned long long f = 0;
@@ -501,19 +550,23 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const LdsMap& 
       if (b) f ^= g.lmask[j];
     }
   }
-  write_flips(g, block_xor64(L, f), flips);
+  flip_fold(L, f);
+  flip_write(g, L, flips);
 }
 
 // Shot output from a global bit-vector.
-__device__ __forceinline__ void emit_from_bits(const DevGraph& g, const LdsMap& L,
+__device__ __forceinline__ void emit_from_bits(const DevGraph& g, const Lds& L,
                                                const uint32_t* bits, uint8_t* corr, uint8_t* flips) {
+  if (threadIdx.x < 4) L.u32(kOffFlips)[threadIdx.x] = 0u;
+  __syncthreads();
   unsigned long long f = 0;
   for (int j = threadIdx.x; j < g.n; j += blockDim.x) {
     const uint32_t b = (bits[j >> 5] >> (j & 31)) & 1u;
     corr[j] = (uint8_t)b;
     if (b) f ^= g.lmask[j];
   }
-  write_flips(g, block_xor64(L, f), flips);
+  flip_fold(L, f);
+  flip_write(g, L, flips);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,7 +602,7 @@ __device__ __forceinline__ char* slot_ptr(const BatchArgs& a, int ctx, int s) {
 __device__ __forceinline__ uint32_t dev_clock() { return (uint32_t)wall_clock64(); }
 
 // Write the shot's outputs from a slot's hard-decision bits and retire the context.
-__device__ __forceinline__ void finish_deep(const BatchArgs& a, const LdsMap& L, int ctx,
+__device__ __forceinline__ void finish_deep(const BatchArgs& a, const Lds& L, int ctx,
                                             long long shot, const uint32_t* bits, int converged,
                                             uint32_t t_start) {
   const DevGraph& g = a.g;
@@ -568,7 +621,7 @@ __device__ __forceinline__ void finish_deep(const BatchArgs& a, const LdsMap& L,
 
 // Selection at the end of a round (Algorithm 3 with Appendix B), run by the
 // workgroup that finished the round's last child.
-__device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L, int ctx) {
+__device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, int ctx) {
   const DevGraph& g = a.g;
   Ctx* C = a.ctxs + ctx;
   const int tid = threadIdx.x;
@@ -576,6 +629,8 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L
   const long long shot = C->shot;
   const uint32_t t0 = C->t_start;
   const int nch = 2 * nset;
+  int32_t* order = L.i32(kOffOrder);
+  int32_t* misc = L.misc();
   if (best != 0x7FFFFFFF) {
     // First converged child in exploration order.
     const int s = C->slots[nset + best];
@@ -595,15 +650,16 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L
         if (sq > si || (sq == si && q < i)) ++rank;
       }
     }
-    L.order[i] = rank;
+    order[i] = rank;
   }
   __syncthreads();
   if (tid == 0) {
     int cnt = 0;
-    int32_t* byrank = L.byrank;
+    int32_t* byrank = L.i32(kOffByrank);
+    int32_t* mark = L.i32(kOffMark);
     for (int i = 0; i < nch; ++i)
-      if (L.order[i] >= 0) {
-        byrank[L.order[i]] = i;
+      if (order[i] >= 0) {
+        byrank[order[i]] = i;
         ++cnt;
       }
     const int ns = cnt < a.bw ? cnt : a.bw;
@@ -615,22 +671,22 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L
       for (int q = 0; q < ns; ++q) nbranch += C->child_next_pos[byrank[q]] >= 0;
       action = nbranch > 0 ? 0 : 2;
     }
-    L.misc[8] = action;
-    L.misc[9] = ns > 0 ? C->slots[nset + byrank[0]] : 0;
+    misc[8] = action;
+    misc[9] = ns > 0 ? C->slots[nset + byrank[0]] : 0;
     if (action == 0) {
       const int ntot = 3 * a.bw;
-      int32_t* newslots = L.newslots;
-      for (int s = 0; s < ntot; ++s) L.mark[s] = 0;
+      int32_t* newslots = L.i32(kOffNewslots);
+      for (int s = 0; s < ntot; ++s) mark[s] = 0;
       for (int q = 0; q < ns; ++q) {
         const int c = byrank[q];
         newslots[q] = C->slots[nset + c];
-        L.mark[newslots[q]] = 1;
+        mark[newslots[q]] = 1;
         C->parent_next_pos[q] = C->child_next_pos[c];
       }
       int k = ns;
       for (int q = 0; q < ntot; ++q) {
         const int s = C->slots[q];
-        if (!L.mark[s]) newslots[k++] = s;
+        if (!mark[s]) newslots[k++] = s;
       }
       for (int q = 0; q < ntot; ++q) C->slots[q] = newslots[q];
       C->nset = ns;
@@ -646,8 +702,8 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L
     }
   }
   __syncthreads();
-  const int action = L.misc[8];
-  const int s0 = L.misc[9];
+  const int action = misc[8];
+  const int s0 = misc[9];
   __syncthreads();
   if (action == 1) {
     finish_deep(a, L, ctx, shot, (const uint32_t*)(slot_ptr(a, ctx, s0) + slot_ehat_off(g)), 0, t0);
@@ -660,7 +716,7 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const LdsMap& L
 // Initial BP run of a shot.  `ctx` is the workgroup's spare context; the
 // return value tells whether the shot went deep and consumed it.
 template <int CPT, int PW>
-__device__ __forceinline__ bool process_init(const BatchArgs& a, const LdsMap& L,
+__device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
                                              const Res<CPT, PW>& R, long long shot, int ctx,
                                              unsigned long long& nruns, unsigned long long& niters) {
   const DevGraph& g = a.g;
@@ -709,7 +765,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const LdsMap& L
 }
 
 template <int CPT, int PW>
-__device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& L,
+__device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
                                               const Res<CPT, PW>& R, uint32_t item,
                                               unsigned long long& nruns,
                                               unsigned long long& niters) {
@@ -717,19 +773,20 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& 
   const int ctx = (int)(item >> 8), c = (int)(item & 255u);
   Ctx* C = a.ctxs + ctx;
   const int tid = threadIdx.x;
+  int32_t* misc = L.misc();
   if (tid == 0) {
     __threadfence();
-    L.misc[10] = C->nset;
-    L.misc[11] = C->slots[c >> 1];
-    L.misc[12] = C->slots[C->nset + c];
-    L.misc[13] = C->parent_next_pos[c >> 1];
-    L.misc[14] = C->shot;
-    L.misc[15] = __hip_atomic_load(&C->best_gen, __ATOMIC_RELAXED, AGENT) < c;
+    misc[10] = C->nset;
+    misc[11] = C->slots[c >> 1];
+    misc[12] = C->slots[C->nset + c];
+    misc[13] = C->parent_next_pos[c >> 1];
+    misc[14] = C->shot;
+    misc[15] = __hip_atomic_load(&C->best_gen, __ATOMIC_RELAXED, AGENT) < c;
   }
   __syncthreads();
   __threadfence();
-  const int ps = L.misc[11], ms = L.misc[12], npos = L.misc[13], skip = L.misc[15];
-  const long long shot = L.misc[14];
+  const int ps = misc[11], ms = misc[12], npos = misc[13], skip = misc[15];
+  const long long shot = misc[14];
   char* pslot = slot_ptr(a, ctx, ps);
   char* mslot = slot_ptr(a, ctx, ms);
   int state = 2;
@@ -739,7 +796,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& 
     int32_t* mp = (int32_t*)(mslot + slot_pairs_off(g) + 16);
     for (int q = tid; q <= np; q += blockDim.x) {
       const int32_t v = q < np ? pp[q] : ((npos << 1) | (c & 1));
-      L.pairs[q] = v;
+      L.pairs()[q] = v;
       mp[q] = v;
     }
     if (tid == 0) *(int32_t*)(mslot + slot_pairs_off(g)) = np + 1;
@@ -775,10 +832,10 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& 
   __syncthreads();
   if (tid == 0) {
     const int left = __hip_atomic_fetch_add(&C->pending, -1, __ATOMIC_ACQ_REL, AGENT);
-    L.misc[16] = (left == 1);
+    misc[16] = (left == 1);
   }
   __syncthreads();
-  const int last = L.misc[16];
+  const int last = misc[16];
   __syncthreads();
   if (last) {
     __threadfence();
@@ -790,9 +847,9 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const LdsMap& 
 // the shot whose initial run fails; it claims shots in chunks and prefers
 // queued child runs of shots already in the beam.
 template <int CPT, int PW>
-__global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
+__global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
-  const LdsMap L = lds_map(a.g, lds_raw);
+  const Lds L{lds_raw};
   Res<CPT, PW> R;
   load_res<CPT, PW>(a.g, L, R);
   unsigned long long nruns = 0, niters = 0;
@@ -800,14 +857,18 @@ __global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
   long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
-  for (;;) {
+  bool exhausted = false;         // thread 0 only
+  int32_t* misc = L.misc();
+  for (int it = 0;; ++it) {
+    opaque_res<CPT, PW>(R);
+    int32_t* box = misc + 20 + 4 * (it & 1);  // alternating slots: one barrier per step
     if (tid == 0) {
       int kind = 0;
       uint32_t item = 0;
       long long shot = -1;
       if (ring_pop(&a.st->work, a.work_ring, &item)) {
         kind = 1;
-      } else {
+      } else if (!exhausted) {
         if (spare < 0) {
           uint32_t cx;
           if (ring_pop(&a.st->ctxq, a.ctx_ring, &cx)) spare = (int)cx;
@@ -818,6 +879,7 @@ __global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
                 &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
             cnext = (long long)b;
             cend = (long long)b + kChunk < a.shots ? (long long)b + kChunk : a.shots;
+            if (cnext >= a.shots) exhausted = true;
           }
           if (cnext < cend) {
             kind = 2;
@@ -832,16 +894,15 @@ __global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
         else
           __builtin_amdgcn_s_sleep(8);
       }
-      L.misc[20] = kind;
-      L.misc[21] = (int)item;
-      L.misc[22] = (int)(shot & 0xFFFFFFFF);
-      L.misc[23] = (int)(shot >> 32);
+      box[0] = kind;
+      box[1] = (int)item;
+      box[2] = (int)(shot & 0xFFFFFFFF);
+      box[3] = (int)(shot >> 32);
     }
     __syncthreads();
-    const int kind = L.misc[20];
-    const uint32_t item = (uint32_t)L.misc[21];
-    const long long shot = (long long)(uint32_t)L.misc[22] | ((long long)L.misc[23] << 32);
-    __syncthreads();
+    const int kind = box[0];
+    const uint32_t item = (uint32_t)box[1];
+    const long long shot = (long long)(uint32_t)box[2] | ((long long)box[3] << 32);
     if (kind == 3) break;
     if (kind == 2) {
       if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters) && tid == 0) spare = -1;
@@ -857,14 +918,14 @@ __global__ void __launch_bounds__(1024) k_batched(BatchArgs a) {
 
 // A single BP run launched on its own (grid of one workgroup).
 template <int CPT, int PW>
-__global__ void __launch_bounds__(1024) k_single(SingleArgs a) {
+__global__ void __launch_bounds__(max_block_for(CPT)) k_single(SingleArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   const DevGraph& g = a.g;
-  const LdsMap L = lds_map(g, lds_raw);
+  const Lds L{lds_raw};
   Res<CPT, PW> R;
   load_res<CPT, PW>(g, L, R);
   const int tid = threadIdx.x, B = blockDim.x;
-  for (int q = tid; q < a.npairs; q += B) L.pairs[q] = a.pairs[q];
+  for (int q = tid; q < a.npairs; q += B) L.pairs()[q] = a.pairs[q];
   __syncthreads();
   RunRegs<CPT> rg;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, a.parent, a.parent_csc, a.npairs, a.syn, a.max_iters,
@@ -885,7 +946,7 @@ __global__ void __launch_bounds__(1024) k_single(SingleArgs a) {
       a.out_ehat[j] = (uint8_t)(((rr.conv ? filled : (rg.ebits & ~rg.mbits)) >> c) & 1u);
     if (a.out_csc) {
       const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
-      for (int e = 0; e < dg; ++e) a.out_csc[st + e] = L.msg[g.cedge[st + e] & 0xFFFFu];
+      for (int e = 0; e < dg; ++e) a.out_csc[st + e] = L.msg()[g.cedge[st + e] & 0xFFFFu];
     }
   }
   if (tid == 0) {
@@ -986,5 +1047,9 @@ BSD_DECLARE_PW(4)
     case 14: return F<14> ARGS;                 \
     case 15: return F<15> ARGS;                 \
     case 16: return F<16> ARGS;                 \
+    case 17: return F<17> ARGS;                 \
+    case 20: return F<20> ARGS;                 \
+    case 24: return F<24> ARGS;                 \
+    case 32: return F<32> ARGS;                 \
     default: return hipErrorInvalidValue;       \
   }

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -399,7 +400,7 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   if (!out) return fail(BSD_EINVAL, "out is NULL");
   *out = nullptr;
   if (m <= 0 || n <= 0 || k < 0) return fail(BSD_EINVAL, "m, n must be > 0 and k >= 0");
-  if (m >= 65536) return fail(BSD_EINVAL, "m must be < 65536");
+  if (m > 2048) return fail(BSD_EINVAL, "m must be <= 2048");
   if (k > 64) return fail(BSD_EINVAL, "k must be <= 64");
   if (!h_colptr || !h_rowidx || !p) return fail(BSD_EINVAL, "H and p are required");
   if (k > 0 && (!l_colptr || !l_rowidx)) return fail(BSD_EINVAL, "A is required when k > 0");
@@ -506,7 +507,7 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   // Launch geometry: one BP run per workgroup; columns c * block + tid,
   // detector rows of rank q * block + tid (q < 2).
   c->lds = lds_bytes_for(g);
-  if (c->lds > (size_t)kLdsBytes || nnz > 65535) {
+  if (c->lds > (size_t)kLdsBytes || g.nnz_pad + 64 > 65535 || maxdeg > 252) {
     bsd_code_destroy(c);
     return fail(BSD_EINVAL, "graph too large: %d edges need %zu bytes of LDS (limit %d)", nnz,
                 c->lds, kLdsBytes);
@@ -514,17 +515,24 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   int maxdeg_col = 1;
   for (int j = 0; j < n; ++j) maxdeg_col = std::max(maxdeg_col, h_colptr[j + 1] - h_colptr[j]);
   c->pw = (maxdeg_col + 1) / 2;
+  // A workgroup of 1024 lanes holds up to 9 columns per lane in registers;
+  // beyond that 512 lanes get twice the registers.  Small graphs share a CU
+  // between many single-wave workgroups.  BSD_BLOCK overrides the choice.
+  auto cpt_for = [&](int b) { return supported_cpt((n + b - 1) / b); };
   if (c->lds > 64 * 1024) {
-    c->block = 1024;
+    c->block = cpt_for(1024) <= 9 ? 1024 : 512;
   } else {
     c->block = 64;
-    while ((n + c->block - 1) / c->block > kMaxCpt || m > 2 * c->block) c->block *= 2;
+    while (cpt_for(c->block) > 16 || m > 2 * c->block) c->block *= 2;
   }
-  c->cpt = (n + c->block - 1) / c->block;
-  if (c->block > 1024 || c->cpt > kMaxCpt || m > 2 * c->block) {
+  if (const char* eb = getenv("BSD_BLOCK")) {
+    const int b = atoi(eb);
+    if (b >= 64 && b <= 1024 && b % 64 == 0 && (b & (b - 1)) == 0) c->block = b;
+  }
+  c->cpt = cpt_for(c->block);
+  if (c->block > 1024 || c->cpt < 0 || m > 2 * c->block || c->block > max_block_for_cpt(c->cpt)) {
     bsd_code_destroy(c);
-    return fail(BSD_EINVAL, "graph too large: n = %d (limit %d), m = %d (limit 2048)", n,
-                kMaxCpt * 1024, m);
+    return fail(BSD_EINVAL, "graph too large: n = %d, m = %d for the available kernels", n, m);
   }
   hipError_t he = set_kernel_limits(c->cpt, c->pw, c->lds);
   if (he != hipSuccess) {

@@ -13,7 +13,7 @@ constexpr int kMaxBw = 64;         // largest beam width
 constexpr int kMaxRounds = 64;     // largest number of fixed nodes on a path
 constexpr int kMaxResults = 64;    // largest num_results
 constexpr int kMaxWaves = 16;      // 1024 threads per workgroup at most
-constexpr int kMaxCpt = 16;        // columns per thread at most
+constexpr int kMaxCpt = 32;        // columns per thread at most
 constexpr float kLlrMax = 1e30f;   // saturation of every message
 constexpr int kLdsBytes = 160 * 1024;
 
@@ -159,5 +159,16 @@ hipError_t set_kernel_limits(int cpt, int pw, size_t lds);
 hipError_t batched_occupancy(int cpt, int pw, int block, size_t lds, int* blocks_per_cu);
 
 size_t lds_bytes_for(const DevGraph& g);
+
+// Columns-per-lane values that have compiled kernels: the smallest one >= c.
+inline int supported_cpt(int c) {
+  if (c <= 16) return c < 1 ? 1 : c;
+  if (c <= 17) return 17;
+  if (c <= 20) return 20;
+  if (c <= 24) return 24;
+  if (c <= 32) return 32;
+  return -1;
+}
+inline int max_block_for_cpt(int cpt) { return cpt > 9 ? 512 : 1024; }
 
 }  // namespace bsd

@@ -63,9 +63,7 @@ __global__ void k_emit(EmitArgs a) {
 
 }  // namespace
 
-size_t lds_bytes_for(const DevGraph& g) {
-  return ((size_t)g.nnz_pad * 4 + dev::lds_tail_bytes(g) + 15) & ~(size_t)15;
-}
+size_t lds_bytes_for(const DevGraph& g) { return (dev::lds_need(g) + 15) & ~(size_t)15; }
 
 #define BSD_PW_SWITCH(pw, CALL)                  \
   switch (pw) {                                  \
