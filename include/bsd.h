@@ -57,7 +57,8 @@ typedef struct bsd_code_s* bsd_code;
  *                    log((1-p_j)/p_j) is returned (Appendix B)
  *   alpha            scaling of the detector-to-error messages of eq. (1);
  *                    1.0 is eq. (1) as printed (> 0, finite)
- *   mode             a bsd_mode value */
+ *   mode             a bsd_mode value
+ *   flags            bsd_flag bits */
 typedef struct {
   int32_t max_rounds;
   int32_t beam_width;
@@ -66,7 +67,14 @@ typedef struct {
   int32_t num_results;
   float alpha;
   int32_t mode;
+  int32_t flags; /* bitwise OR of bsd_flag values (0 = defaults) */
 } bsd_params;
+
+typedef enum {
+  /* Batched mode: record the call's kernels in a HIP graph and replay it
+   * when a later call repeats the same buffers, shot count and parameters. */
+  BSD_FLAG_GRAPH = 1
+} bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */
 typedef struct {
@@ -89,9 +97,10 @@ typedef struct {
  *   l_rowidx     host, int32: CSC row indices of A
  *   out          receives the handle
  * The caller keeps ownership of every array; they may be freed on return.
- * Limits: m < 65536, k <= 64, column degree <= 8, row degree <= 255, and
- * the fp32 edge messages of one BP run (4 * nnz bytes) must fit in the
- * 160 KB LDS of one compute unit (nnz <= 39936).
+ * Limits: m <= 2048, n <= 16384, k <= 64, column degree <= 8, row degree
+ * <= 252, and the fp32 edge messages of one BP run (4 * nnz bytes plus
+ * about 7 KB of per-run state) must fit in the 160 KB LDS of one compute
+ * unit (nnz <= 39100).
  * Errors: BSD_EINVAL for malformed CSC, p outside (0,1) or limits exceeded;
  * BSD_ENOMEM, BSD_EDEVICE. */
 bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_colptr,
@@ -144,6 +153,18 @@ bsd_status bsd_bp_run(bsd_code code, const float* e_start, const int32_t* pairs,
                       int32_t stop_on_converge, float* e_out, float* sum_llr, uint8_t* ehat,
                       int32_t* iters, int32_t* converged, int32_t* next_pos, float* score,
                       void* stream);
+
+/* Choose the batched kernel's workgroup size and number of resident
+ * workgroups for this code and parameters by timing each admissible choice
+ * on the given syndromes (device, uint8 [shots x m]), and keep the fastest
+ * for later calls.  When the environment variable BSD_TUNE_CACHE names a
+ * file, choices are read from and appended to it, keyed by a digest of
+ * (H, p, parameters, device).  Outputs (host, may be NULL): the chosen
+ * block size, grid size and the best time of one call in milliseconds.
+ * Errors: as bsd_decode. */
+bsd_status bsd_code_autotune(bsd_code code, const bsd_params* prm, int64_t shots,
+                             const uint8_t* syndromes, int32_t* block_threads,
+                             int32_t* grid_blocks, float* best_ms, void* stream);
 
 /* Geometry of a code handle: nnz of H and the threads per workgroup and
  * workgroups the batched kernel will use.  Any pointer may be NULL. */

@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "bsd.h")
 
 BSD_OK, BSD_EINVAL, BSD_ENOMEM, BSD_EDEVICE, BSD_EBUSY = 0, -1, -2, -3, -4
 MODE_BATCHED, MODE_PLAIN = 0, 1
+FLAG_GRAPH = 1
 _lib = None
 
 
@@ -31,7 +32,8 @@ class BsdError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("max_rounds", C.c_int32), ("beam_width", C.c_int32),
                 ("initial_iters", C.c_int32), ("iters_per_round", C.c_int32),
-                ("num_results", C.c_int32), ("alpha", C.c_float), ("mode", C.c_int32)]
+                ("num_results", C.c_int32), ("alpha", C.c_float), ("mode", C.c_int32),
+                ("flags", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -67,6 +69,9 @@ def load():
     lib.bsd_decode.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P]
     lib.bsd_decode_ex.restype = C.c_int
     lib.bsd_decode_ex.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P, C.POINTER(Stats), P]
+    lib.bsd_code_autotune.restype = C.c_int
+    lib.bsd_code_autotune.argtypes = [P, C.POINTER(Params), i64, P, i32p, i32p,
+                                      C.POINTER(C.c_float), P]
     lib.bsd_bp_run.restype = C.c_int
     lib.bsd_bp_run.argtypes = [P, P, i32p, i32, P, i32, C.c_float, i32, P, P, P, i32p, i32p, i32p,
                                C.POINTER(C.c_float), P]
@@ -98,9 +103,9 @@ def _stream(stream):
 
 
 def make_params(max_rounds, beam_width, initial_iters, iters_per_round, num_results=1,
-                alpha=0.625, mode=MODE_BATCHED) -> Params:
+                alpha=0.625, mode=MODE_BATCHED, flags=0) -> Params:
     return Params(int(max_rounds), int(beam_width), int(initial_iters), int(iters_per_round),
-                  int(num_results), float(alpha), int(mode))
+                  int(num_results), float(alpha), int(mode), int(flags))
 
 
 class Code:
@@ -179,6 +184,17 @@ class Code:
         if latency:
             res["latency_ticks"] = lat
         return res
+
+    def autotune(self, syndromes, params: Params, stream=None) -> dict:
+        """Time the admissible launch geometries on `syndromes` and keep the fastest."""
+        import torch
+        if syndromes.dtype != torch.uint8 or not syndromes.is_cuda or syndromes.dim() != 2:
+            raise ValueError("syndromes must be a [shots, m] uint8 CUDA tensor")
+        blk, grid, ms = C.c_int32(), C.c_int32(), C.c_float()
+        _check(self._lib.bsd_code_autotune(self._h, C.byref(params), syndromes.shape[0],
+                                           _ptr(syndromes.contiguous()), C.byref(blk),
+                                           C.byref(grid), C.byref(ms), _stream(stream)))
+        return {"block": blk.value, "grid": grid.value, "ms": ms.value}
 
     def bp_run(self, syndrome, max_iters, alpha=0.625, e_start=None, pairs=(), stop=True,
                stream=None):

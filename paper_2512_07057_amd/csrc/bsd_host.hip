@@ -92,6 +92,12 @@ struct bsd_code_s {
   std::mutex mu;
   std::atomic<int> busy{0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // HIP graph of the last batched call (BSD_FLAG_GRAPH).
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<char> gkey;
+  int grid_frac_half = 0;  // autotuner: use half the resident workgroups
 };
 
 namespace {
@@ -111,8 +117,17 @@ void free_workspace(bsd_code c) {
   c->ws_bw = 0;
 }
 
+void drop_graph(bsd_code c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gkey.clear();
+}
+
 bsd_status ensure_batched(bsd_code c, int bw) {
-  if (c->ws_bw >= bw && c->st) return BSD_OK;
+  if (c->ws_bw >= bw && c->st && c->nctx >= c->grid + 64) return BSD_OK;
+  drop_graph(c);
   free_workspace(c);
   const int nctx = c->grid + 64;
   const int per = 3 * bw + 1;
@@ -364,10 +379,37 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.slots = c->slots;
   a.slot_stride = c->slot_stride;
   a.slots_per_ctx = 3 * c->ws_bw + 1;
-  HIP_OR_FAIL(launch_batch_reset(a, s));
-  HIP_OR_FAIL(hipEventRecord(c->ev0, s));
-  HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
-  HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+  if (p->flags & BSD_FLAG_GRAPH) {
+    // Replay the recorded reset + decode kernels when the arguments repeat.
+    std::vector<char> key(sizeof a + 3 * sizeof(int));
+    std::memcpy(key.data(), &a, sizeof a);
+    const int geo[3] = {c->grid, c->block, c->cpt};
+    std::memcpy(key.data() + sizeof a, geo, sizeof geo);
+    if (!c->gexec || key != c->gkey) {
+      drop_graph(c);
+      if (!c->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      HIP_OR_FAIL(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = launch_batch_reset(a, c->cap_stream);
+      hipError_t e2 = launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, c->cap_stream);
+      hipGraph_t gr = nullptr;
+      hipError_t e3 = hipStreamEndCapture(c->cap_stream, &gr);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        if (gr) hipGraphDestroy(gr);
+        return fail(BSD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
+      }
+      c->graph = gr;
+      HIP_OR_FAIL(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+      c->gkey = key;
+    }
+    HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+    HIP_OR_FAIL(hipGraphLaunch(c->gexec, s));
+    HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+  } else {
+    HIP_OR_FAIL(launch_batch_reset(a, s));
+    HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+    HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
+    HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+  }
   HIP_OR_FAIL(hipMemcpyAsync(c->st_host, c->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
   const BatchState& h = *c->st_host;
@@ -384,6 +426,34 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
     stats->kernel_ms = ms;
   }
   return BSD_OK;
+}
+
+// Workgroup size `block` and resident workgroups (all that fit, or half).
+bsd_status set_geometry(bsd_code c, int block, int half) {
+  const DevGraph& g = c->g;
+  const int cpt = supported_cpt((g.n + block - 1) / block);
+  if (block < 64 || block > 1024 || cpt < 0 || g.m > 2 * block || block > max_block_for_cpt(cpt))
+    return fail(BSD_EINVAL, "no kernel for %d threads with n = %d, m = %d", block, g.n, g.m);
+  hipError_t he = set_kernel_limits(cpt, c->pw, c->lds);
+  if (he != hipSuccess) return fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
+  int per_cu = 0, ncu = 0;
+  he = batched_occupancy(cpt, c->pw, block, c->lds, &per_cu);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (he != hipSuccess || per_cu < 1)
+    return fail(BSD_EDEVICE, "occupancy query failed: %s (blocks per CU %d)", hipGetErrorString(he), per_cu);
+  const int grid = half && per_cu > 1 ? (per_cu / 2) * ncu : per_cu * ncu;
+  if (grid != c->grid || block != c->block) drop_graph(c);
+  c->block = block;
+  c->cpt = cpt;
+  c->grid = grid;
+  c->grid_frac_half = half && per_cu > 1;
+  return BSD_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
 }
 
 }  // namespace
@@ -517,36 +587,27 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   c->pw = (maxdeg_col + 1) / 2;
   // A workgroup of 1024 lanes holds up to 9 columns per lane in registers;
   // beyond that 512 lanes get twice the registers.  Small graphs share a CU
-  // between many single-wave workgroups.  BSD_BLOCK overrides the choice.
-  auto cpt_for = [&](int b) { return supported_cpt((n + b - 1) / b); };
+  // between many single-wave workgroups.  BSD_BLOCK overrides the choice;
+  // bsd_code_autotune measures.
+  int block;
   if (c->lds > 64 * 1024) {
-    c->block = cpt_for(1024) <= 9 ? 1024 : 512;
+    block = supported_cpt((n + 1023) / 1024) <= 9 ? 1024 : 512;
   } else {
-    c->block = 64;
-    while (cpt_for(c->block) > 16 || m > 2 * c->block) c->block *= 2;
+    block = 64;
+    while (supported_cpt((n + block - 1) / block) > 16 || m > 2 * block) block *= 2;
   }
   if (const char* eb = getenv("BSD_BLOCK")) {
     const int b = atoi(eb);
-    if (b >= 64 && b <= 1024 && b % 64 == 0 && (b & (b - 1)) == 0) c->block = b;
+    if (b >= 64 && b <= 1024 && (b & (b - 1)) == 0) block = b;
   }
-  c->cpt = cpt_for(c->block);
-  if (c->block > 1024 || c->cpt < 0 || m > 2 * c->block || c->block > max_block_for_cpt(c->cpt)) {
-    bsd_code_destroy(c);
-    return fail(BSD_EINVAL, "graph too large: n = %d, m = %d for the available kernels", n, m);
+  {
+    bsd_status gs = set_geometry(c, block, 0);
+    if (gs != BSD_OK) {
+      std::string msg = g_err;
+      bsd_code_destroy(c);
+      return fail(gs, "%s", msg.c_str());
+    }
   }
-  hipError_t he = set_kernel_limits(c->cpt, c->pw, c->lds);
-  if (he != hipSuccess) {
-    bsd_code_destroy(c);
-    return fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
-  }
-  int per_cu = 0, ncu = 0;
-  he = batched_occupancy(c->cpt, c->pw, c->block, c->lds, &per_cu);
-  if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
-  if (he != hipSuccess || per_cu < 1) {
-    bsd_code_destroy(c);
-    return fail(BSD_EDEVICE, "occupancy query failed: %s (blocks per CU %d)", hipGetErrorString(he), per_cu);
-  }
-  c->grid = per_cu * ncu;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     bsd_code_destroy(c);
     return fail(BSD_EDEVICE, "hipEventCreate failed");
@@ -558,6 +619,8 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
 bsd_status bsd_code_destroy(bsd_code c) {
   if (!c) return BSD_OK;
   if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
+  drop_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   free_workspace(c);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);
@@ -664,6 +727,103 @@ bsd_status bsd_bp_run(bsd_code c, const float* e_start, const int32_t* pairs, in
   if (converged) *converged = res[1];
   if (next_pos) *next_pos = res[2];
   if (score) std::memcpy(score, &res[3], 4);
+  return BSD_OK;
+}
+
+bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                             int32_t* out_block, int32_t* out_grid, float* out_ms, void* stream) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  bsd_status st = check_params(c, p);
+  if (st != BSD_OK) return st;
+  if (shots <= 0 || !syn) return fail(BSD_EINVAL, "autotune needs a non-empty batch of syndromes");
+  hipDeviceProp_t prop;
+  HIP_OR_FAIL(hipGetDeviceProperties(&prop, c->device));
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &c->g.m, sizeof c->g.m);
+  h = fnv1a(h, &c->g.n, sizeof c->g.n);
+  h = fnv1a(h, c->colptr.data(), c->colptr.size() * 4);
+  h = fnv1a(h, c->rowidx.data(), c->rowidx.size() * 4);
+  const int32_t pk[5] = {p->max_rounds, p->beam_width, p->initial_iters, p->iters_per_round,
+                         p->num_results};
+  h = fnv1a(h, pk, sizeof pk);
+  h = fnv1a(h, prop.gcnArchName, strlen(prop.gcnArchName));
+  const char* cache = getenv("BSD_TUNE_CACHE");
+  if (cache) {
+    if (FILE* f = fopen(cache, "r")) {
+      unsigned long long key;
+      int b, half;
+      float ms;
+      bool hit = false;
+      while (fscanf(f, "%llx %d %d %f", &key, &b, &half, &ms) == 4) {
+        if (key == h) {
+          std::lock_guard<std::mutex> lock(c->mu);
+          if (set_geometry(c, b, half) == BSD_OK) {
+            hit = true;
+            if (out_ms) *out_ms = ms;
+          }
+        }
+      }
+      fclose(f);
+      if (hit) {
+        if (out_block) *out_block = c->block;
+        if (out_grid) *out_grid = c->grid;
+        return BSD_OK;
+      }
+    }
+  }
+  uint8_t *corr = nullptr, *flips = nullptr, *conv = nullptr;
+  if (hipMalloc((void**)&corr, (size_t)shots * c->g.n) != hipSuccess ||
+      hipMalloc((void**)&flips, (size_t)shots * std::max(c->g.k, 1)) != hipSuccess ||
+      hipMalloc((void**)&conv, (size_t)shots) != hipSuccess) {
+    hipFree(corr);
+    hipFree(flips);
+    (void)hipGetLastError();
+    return fail(BSD_ENOMEM, "autotune scratch allocation failed");
+  }
+  const int b0 = c->block, h0 = c->grid_frac_half;
+  int best_b = b0, best_h = h0;
+  float best_ms = 3.0e38f;
+  bsd_params q = *p;
+  q.mode = BSD_MODE_BATCHED;
+  q.flags = 0;
+  for (int b = 64; b <= 1024 && st == BSD_OK; b *= 2) {
+    for (int half = 0; half <= 1; ++half) {
+      {
+        std::lock_guard<std::mutex> lock(c->mu);
+        if (set_geometry(c, b, half) != BSD_OK) break;
+        if (half && !c->grid_frac_half) break;
+      }
+      float ms_min = 3.0e38f;
+      for (int rep = 0; rep < 3 && st == BSD_OK; ++rep) {
+        bsd_stats sts;
+        st = bsd_decode_ex(c, &q, shots, syn, corr, flips, conv, stream, &sts, nullptr);
+        if (st == BSD_OK && rep > 0) ms_min = std::min(ms_min, (float)sts.kernel_ms);
+      }
+      if (st == BSD_OK && ms_min < best_ms) {
+        best_ms = ms_min;
+        best_b = b;
+        best_h = half;
+      }
+    }
+  }
+  hipFree(corr);
+  hipFree(flips);
+  hipFree(conv);
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    bsd_status s2 = set_geometry(c, best_b, best_h);
+    if (st == BSD_OK) st = s2;
+  }
+  if (st != BSD_OK) return st;
+  if (cache) {
+    if (FILE* f = fopen(cache, "a")) {
+      fprintf(f, "%llx %d %d %.6f\n", (unsigned long long)h, best_b, best_h, best_ms);
+      fclose(f);
+    }
+  }
+  if (out_block) *out_block = c->block;
+  if (out_grid) *out_grid = c->grid;
+  if (out_ms) *out_ms = best_ms;
   return BSD_OK;
 }
 

@@ -1,0 +1,69 @@
+"""Batched runtime on the GPU: HIP-graph replay and the launch-geometry
+autotuner leave every output unchanged."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gpu_common as gc
+from bsd_inputs import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bsd():
+    import paper_2512_07057_amd as m
+    m.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+def _np(out):
+    return {k: out[k].cpu().numpy() for k in ("corrections", "flips", "converged")}
+
+
+def test_graph_replay_matches_eager(bsd):
+    W = workloads.WORKLOADS["W1"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    a = torch.from_numpy(gc.samples("W1", 1500, seed=11)["syndromes"]).cuda()
+    b = torch.from_numpy(gc.samples("W1", 1500, seed=12)["syndromes"]).cuda()
+    P = W.params
+    eager = gc.params_for(bsd, P)
+    graph = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                            1, P.alpha, bsd.MODE_BATCHED, bsd.FLAG_GRAPH)
+    ref_a = _np(code.decode(a, eager))
+    ref_b = _np(code.decode(b, eager))
+    out = {"corrections": torch.empty((1500, code.n), dtype=torch.uint8, device="cuda"),
+           "flips": torch.empty((1500, code.k), dtype=torch.uint8, device="cuda"),
+           "converged": torch.empty((1500,), dtype=torch.uint8, device="cuda")}
+    for rep in range(4):
+        gc.log("graph replay", rep)
+        out["corrections"].fill_(7)
+        got = _np(code.decode(a, graph, out=out))
+        for k in ref_a:
+            np.testing.assert_array_equal(got[k], ref_a[k])
+        # eager work on other data between replays
+        got_b = _np(code.decode(b, eager))
+        for k in ref_b:
+            np.testing.assert_array_equal(got_b[k], ref_b[k])
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("key,wl,shots", [("bb72_cc_p0.03", "W0", 3000),
+                                          ("bb144_cc_p0.05", "W1", 2000),
+                                          ("bb144_st12", "W2", 20000)])
+def test_autotune_keeps_results(bsd, key, wl, shots):
+    W = workloads.WORKLOADS[wl]
+    code = bsd.Code.from_problem(gc.problem(key))
+    syn = torch.from_numpy(gc.samples(wl, shots, seed=13)["syndromes"]).cuda()
+    prm = gc.params_for(bsd, W.params)
+    before = _np(code.decode(syn, prm))
+    info0 = code.info()
+    tuned = code.autotune(syn, prm)
+    gc.log("autotune", wl, "default", info0, "chosen", tuned)
+    assert tuned["block"] in (64, 128, 256, 512, 1024) and tuned["grid"] > 0
+    after = _np(code.decode(syn, prm))
+    for k in before:
+        np.testing.assert_array_equal(after[k], before[k])
