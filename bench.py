@@ -34,10 +34,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bsd_batched_w2.json")
 
 
 def kernel_source_digest() -> str:
+    """Digest of every HIP source and header of the library."""
     h = hashlib.sha256()
-    for f in ("bsd_kernels.hip", "bsd_internal.h", "bsd_host.hip"):
-        with open(os.path.join(ROOT, "paper_2512_07057_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    src = os.path.join(ROOT, "paper_2512_07057_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(src, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 

@@ -73,7 +73,14 @@ typedef struct {
 typedef enum {
   /* Batched mode: record the call's kernels in a HIP graph and replay it
    * when a later call repeats the same buffers, shot count and parameters. */
-  BSD_FLAG_GRAPH = 1
+  BSD_FLAG_GRAPH = 1,
+  /* Compute the check phase of iteration 1 of every initial BP run with
+   * eq. (1).  By default it is taken from a table formed once per (code,
+   * alpha): from the priors, eq. (1) depends on the syndrome only through
+   * the factor (-1)^{s_i}, and the table holds the s = 0 values formed with
+   * the kernels' own single-precision operations.  Results are identical
+   * either way; this flag exists to check that. */
+  BSD_FLAG_DENSE_FIRST = 2
 } bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */

@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "bsd.h")
 BSD_OK, BSD_EINVAL, BSD_ENOMEM, BSD_EDEVICE, BSD_EBUSY = 0, -1, -2, -3, -4
 MODE_BATCHED, MODE_PLAIN = 0, 1
 FLAG_GRAPH = 1
+FLAG_DENSE_FIRST = 2
 _lib = None
 
 

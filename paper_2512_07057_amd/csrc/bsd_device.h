@@ -14,7 +14,8 @@
 //
 // LDS layout: a fixed 7072-byte area of small arrays at offset 0 (constant
 // offsets), then the messages, then one trash word per lane that absorbs
-// stores of absent edges so the inner loops need no branches.
+// stores of absent edges and one word of 0.0 that loads of absent edges
+// read, so the inner loops need no branches.
 //
 // Floating-point order follows the paper's formulas left to right: sums run
 // over neighbours in ascending row index, E of eq. (2) is a literal exclusive
@@ -65,8 +66,18 @@ struct Lds {
   __device__ __forceinline__ uint32_t* resid(int b) const { return u32(kOffResid + 256 * b); }
 };
 
+// After the messages: 64 trash words (stores of absent edges), then one word
+// that stays 0.0 (loads of absent edges).
 __host__ __device__ inline size_t lds_need(const DevGraph& g) {
-  return (size_t)kOffMsg + ((size_t)g.nnz_pad + 64) * 4;
+  return (size_t)kOffMsg + ((size_t)g.nnz_pad + 68) * 4;
+}
+
+// Barrier for LDS data only: waits for this wave's LDS operations, not for
+// its outstanding global stores.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Graph data of one lane, read once per launch.  Lane tid owns columns
@@ -75,7 +86,7 @@ template <int CPT, int PW>
 struct Res {
   float lam[CPT];
   uint32_t pos[CPT][PW];          // LDS positions of the column's edges (16 bits each, CSC
-                                  // order); absent edges point at the lane's trash word
+                                  // order); absent edges point at the zero word
   uint32_t deg[(CPT + 7) / 8];    // 4 bits per column
   uint32_t dmx[(CPT + 7) / 8];    // 4 bits per column: largest degree in the wave
   uint32_t row[2];                // original row (bits 0..15) | degree << 16 | 1 << 31; 0 past m
@@ -93,7 +104,8 @@ __device__ __forceinline__ void opaque_res(Res<CPT, PW>& R) {
     asm volatile("" : "+v"(R.lam[c]));
   }
 #pragma unroll
-  for (int w = 0; w < (CPT + 7) / 8; ++w) asm volatile("" : "+v"(R.deg[w]), "+v"(R.dmx[w]));
+  for (int w = 0; w < (CPT + 7) / 8; ++w)
+    asm volatile("" : "+v"(R.deg[w]), "+v"(R.dmx[w]));
   asm volatile("" : "+v"(R.row[0]), "+v"(R.row[1]));
 }
 
@@ -140,12 +152,16 @@ __device__ __forceinline__ uint32_t trash_pos(const DevGraph& g) {
   return (uint32_t)g.nnz_pad + (threadIdx.x & 63u);
 }
 
+__device__ __forceinline__ uint32_t zero_pos(const DevGraph& g) { return (uint32_t)g.nnz_pad + 64u; }
+
+
 // Load a lane's graph data (called by every thread, before any run).
 template <int CPT, int PW>
 __device__ __forceinline__ void load_res(const DevGraph& g, const Lds& L, Res<CPT, PW>& R) {
   const int tid = threadIdx.x, B = blockDim.x;
   for (int i = tid; i < 256; i += B) L.i32(kOffDiag)[i] = i <= g.maxdeg_row ? g.diag_ptr[i] : 0;
-  const uint32_t tp = trash_pos(g);
+  if (tid == 0) L.msg()[zero_pos(g)] = 0.f;
+  const uint32_t tp = zero_pos(g);
 #pragma unroll
   for (int w = 0; w < (CPT + 7) / 8; ++w) R.deg[w] = R.dmx[w] = 0u;
 #pragma unroll
@@ -178,11 +194,33 @@ __device__ __forceinline__ void load_res(const DevGraph& g, const Lds& L, Res<CP
   __syncthreads();
 }
 
+// Running least and second least magnitude: m1 <= m2 and |v| joins them.
+// The median of (m1, m2, |v|) is the new second least.  fmed3 takes the
+// absolute value as a free source modifier.
+__device__ __forceinline__ void min2_step(float& m1, float& m2, uint32_t v) {
+  const float a = fabsf(__uint_as_float(v));
+  m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
+  m1 = __builtin_amdgcn_fmed3f(m1, a, -__builtin_inff());
+}
+
+// Output of eq. (1) on one edge holding v: magnitude d2 if |v| is the row
+// minimum m1 (the minimum over the other edges), else d1; sign of the row
+// product times that of v.  Masked edges (+inf) keep their value.
+template <bool MASKED>
+__device__ __forceinline__ uint32_t check_out(uint32_t v, uint32_t sgn, float m1, float d1, float d2) {
+  const float mag = fabsf(__uint_as_float(v)) == m1 ? d2 : d1;
+  const uint32_t d = ((sgn ^ v) & kSignBit) | (__float_as_uint(mag) & ~kSignBit);
+  return (MASKED && v == kInfBits) ? v : d;
+}
+
 // Eq. (1) for the detector rows of rank q * B + tid, in place: E(t-1) -> D(t)
 // on the unmasked edges (masked edges hold +inf and are skipped).  Magnitudes
-// of non-negative floats compare as unsigned integers.  Ranks are sorted by
-// degree, so in a wave every row has at least the last lane's degree and at
-// most the first lane's: that range is the only part that needs predicates.
+// of non-negative floats compare as unsigned integers.  An edge whose
+// magnitude equals the row minimum receives the second minimum: that is the
+// minimum over the other edges whether the minimum is unique or tied.  Ranks
+// are sorted by degree, so in a wave every row has at least the last lane's
+// degree and at most the first lane's: only that range needs predicates.
+template <bool MASKED>
 __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint32_t rowinfo, int r,
                                            float alpha) {
   uint32_t* msg = L.msgu();
@@ -192,35 +230,26 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
   const int kmax = __builtin_amdgcn_readfirstlane(dg);
   if (kmax == 0) return;
   const int kmin = __builtin_amdgcn_readlane(dg, 63);
-  const uint32_t tp = trash_pos(g);
+  const uint32_t tp = trash_pos(g), zp = zero_pos(g);
   uint32_t sgn = dg ? ((L.sprime()[r >> 5] >> (r & 31)) & 1u) << 31 : 0u;
-  uint32_t m1 = __float_as_uint(kLlrMax), m2 = m1;
-  int arg = -1;
+  float m1 = kLlrMax, m2 = kLlrMax;
   int k = 0;
   for (; k + 4 <= kmin; k += 4) {
     const int4 dd = *reinterpret_cast<const int4*>(diag + k);
-    const uint32_t v0 = msg[dd.x + r], v1 = msg[dd.y + r], v2 = msg[dd.z + r], v3 = msg[dd.w + r];
-    const uint32_t vv[4] = {v0, v1, v2, v3};
+    const uint32_t vv[4] = {msg[dd.x + r], msg[dd.y + r], msg[dd.z + r], msg[dd.w + r]};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t a = vv[u] & ~kSignBit;
       sgn ^= vv[u];
-      m2 = min(m2, max(m1, a));
-      arg = a < m1 ? k + u : arg;
-      m1 = min(m1, a);
+      min2_step(m1, m2, vv[u]);
     }
   }
   for (; k < kmax; ++k) {
     const bool ok = k < dg;
-    const uint32_t v = msg[ok ? (uint32_t)(diag[k] + r) : tp];
-    const uint32_t a = ok ? (v & ~kSignBit) : kInfBits;
-    sgn ^= ok ? v : 0u;
-    m2 = min(m2, max(m1, a));
-    arg = a < m1 ? k : arg;
-    m1 = min(m1, a);
+    const uint32_t v = msg[ok ? (uint32_t)(diag[k] + r) : zp];
+    sgn ^= v;
+    min2_step(m1, m2, ok ? v : kInfBits);
   }
-  const uint32_t d1 = __float_as_uint(fminf(alpha * __uint_as_float(m1), kLlrMax));
-  const uint32_t d2 = __float_as_uint(fminf(alpha * __uint_as_float(m2), kLlrMax));
+  const float d1 = fminf(alpha * m1, kLlrMax), d2 = fminf(alpha * m2, kLlrMax);
   k = 0;
   for (; k + 4 <= kmin; k += 4) {
     const int4 dd = *reinterpret_cast<const int4*>(diag + k);
@@ -229,17 +258,12 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
 #pragma unroll
     for (int u = 0; u < 4; ++u) vv[u] = msg[pp[u]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t d = (k + u == arg ? d2 : d1) | ((sgn ^ vv[u]) & kSignBit);
-      msg[pp[u]] = vv[u] == kInfBits ? vv[u] : d;
-    }
+    for (int u = 0; u < 4; ++u) msg[pp[u]] = check_out<MASKED>(vv[u], sgn, m1, d1, d2);
   }
   for (; k < kmax; ++k) {
     const bool ok = k < dg;
     const uint32_t p = ok ? (uint32_t)(diag[k] + r) : tp;
-    const uint32_t v = msg[p];
-    const uint32_t d = (k == arg ? d2 : d1) | ((sgn ^ v) & kSignBit);
-    msg[p] = v == kInfBits ? v : d;
+    msg[p] = check_out<MASKED>(msg[p], sgn, m1, d1, d2);
   }
 }
 
@@ -264,11 +288,10 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_
     asm volatile("" : "+v"(pk[w]));
   }
 #pragma unroll
-  for (int e = 0; e < D; ++e) {
+  for (int e = 0; e < D; ++e) {  // absent edges read the zero word and write the trash word
     p[e] = (pk[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-    const float x = msg[p[e]];
-    d[e] = e < dg ? x : 0.f;
-    p[e] = active ? p[e] : tp;
+    d[e] = msg[p[e]];
+    p[e] = (active && e < dg) ? p[e] : tp;
   }
   float pre = R.lam[c];
 #pragma unroll
@@ -276,7 +299,7 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_
     float x = pre;
 #pragma unroll
     for (int f = e + 1; f < D; ++f) x = x + d[f];
-    msg[p[e]] = fminf(fmaxf(x, -kLlrMax), kLlrMax);
+    msg[p[e]] = __builtin_amdgcn_fmed3f(x, -kLlrMax, kLlrMax);
     pre = pre + d[e];
   }
   const float post = pre;  // eq. (3)
@@ -321,14 +344,22 @@ __device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint3
 // pairs in LDS and synchronised.  Warm start from `parent` (LDS order) or
 // `parent_csc` (CSC order), else from the priors.  When `cancel` is given the
 // run stops early once *cancel < my_gen (a lower generation converged).
+//
+// A run from the priors with no masked node and `fi` enabled takes the check
+// phase of iteration 1 from the table fi->d0: with E(0) = Lambda on every
+// edge, eq. (1) at t = 1 depends on the syndrome only through the factor
+// (-1)^{s_i}, so D(1) is the s = 0 value with its sign flipped on the rows of
+// flipped detectors.  The table holds that value bit for bit as check_rows
+// would form it.
 template <int CPT, int PW>
 __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
                                          const float* parent, const float* parent_csc, int npairs,
                                          const uint8_t* syn, int T, bool stop, float alpha,
                                          const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
-                                         uint32_t* err) {
+                                         uint32_t* err, const FirstIter* fi = nullptr) {
   const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
+  const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
   rg.mbits = rg.vbits = rg.ebits = 0;
   for (int q = 0; q < npairs; ++q) {
     const int pv = L.pairs()[q];
@@ -339,7 +370,9 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
     }
   }
   if (tid < 4) L.u32(kOffFlips)[tid] = 0u;
-  // s by row rank, 64 ranks per wave ballot.
+  // s by row rank, 64 ranks per wave ballot.  A table run also fills the
+  // residual of iteration 1 here (s' = s without masked nodes).
+  uint32_t sbit[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     uint32_t bit = 0;
@@ -348,14 +381,44 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
       if (b > 1u) atomicOr(err, 1u);
       bit = b & 1u;
     }
+    sbit[q] = bit;
     const unsigned long long bal = __ballot(bit);
     if (lane == 0) {
       const int w = (q * B + wave * 64) >> 5;
       if (w < g.words_m) L.sprime()[w] = (uint32_t)bal;
       if (w + 1 < g.words_m) L.sprime()[w + 1] = (uint32_t)(bal >> 32);
+      if (table) {
+        if (w < g.words_m) L.resid(1)[w] = (uint32_t)bal;
+        if (w + 1 < g.words_m) L.resid(1)[w + 1] = (uint32_t)(bal >> 32);
+      }
     }
   }
-  if (parent) {
+  if (table) {
+    // D(1) for the rows of this thread: table value, sign flipped where s_i = 1.
+    const uint32_t* d0 = reinterpret_cast<const uint32_t*>(fi->d0);
+    const int32_t* diag = L.i32(kOffDiag);
+    uint32_t* mu = L.msgu();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = q * B + tid;
+      const int dg = (int)((R.row[q] >> 16) & 0xFFu);
+      const uint32_t fl = sbit[q] << 31;
+      int k = 0;
+      for (; k + 4 <= dg; k += 4) {
+        const int4 dd = *reinterpret_cast<const int4*>(diag + k);
+        const int pp[4] = {dd.x + r, dd.y + r, dd.z + r, dd.w + r};
+        uint32_t vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) vv[u] = d0[pp[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mu[pp[u]] = vv[u] ^ fl;
+      }
+      for (; k < dg; ++k) {
+        const int pq = diag[k] + r;
+        mu[pq] = d0[pq] ^ fl;
+      }
+    }
+  } else if (parent) {
     const float4* src = reinterpret_cast<const float4*>(parent);
     float4* dst = reinterpret_cast<float4*>(msg);
     for (int i = tid; i < g.nnz_pad / 4; i += B) dst[i] = src[i];
@@ -364,13 +427,15 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
   for (int c = 0; c < CPT; ++c) {
     rg.sumllr[c] = 0.f;
     const int j = c * B + tid;
-    if (!parent && j < g.n) {
+    if (!parent && !table && j < g.n) {
+      const int dg = col_deg(R, c);
       if (parent_csc) {
-        const int st = (int)(g.colinfo[j] & 0xFFFFFFu), dg = col_deg(R, c);
+        const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
         for (int e = 0; e < dg; ++e) msg[g.cedge[st + e] & 0xFFFFu] = parent_csc[st + e] + 0.f;
       } else {
 #pragma unroll
-        for (int e = 0; e < 2 * PW; ++e) msg[col_pos(R, c, e)] = R.lam[c];
+        for (int e = 0; e < 2 * PW; ++e)
+          if (e < dg) msg[col_pos(R, c, e)] = R.lam[c];
       }
     }
   }
@@ -398,10 +463,17 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
   RunRes rr{0, 0, 0};
   for (int t = 1; t <= T; ++t) {
     uint32_t* resid = L.resid(t & 1);
-    for (int w = tid; w < g.words_m; w += B) resid[w] = L.sprime()[w];
+    if (!(table && t == 1)) {
+      for (int w = tid; w < g.words_m; w += B) resid[w] = L.sprime()[w];
+      if (npairs) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) check_rows(g, L, R.row[q], q * B + tid, alpha);
-    __syncthreads();
+        for (int q = 0; q < 2; ++q) check_rows<true>(g, L, R.row[q], q * B + tid, alpha);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) check_rows<false>(g, L, R.row[q], q * B + tid, alpha);
+      }
+      __syncthreads();
+    }
     var_phase<CPT, PW>(g, L, resid, R, rg);
     if (tid == 0) {
       int cx = 0;
@@ -529,7 +601,7 @@ __device__ __forceinline__ void flip_fold(const Lds& L, unsigned long long f) {
 }
 
 __device__ __forceinline__ void flip_write(const DevGraph& g, const Lds& L, uint8_t* flips) {
-  __syncthreads();
+  lds_barrier();
   const unsigned long long t =
       (unsigned long long)L.u32(kOffFlips)[0] | ((unsigned long long)L.u32(kOffFlips)[1] << 32);
   for (int r = threadIdx.x; r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
@@ -558,7 +630,7 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, 
 __device__ __forceinline__ void emit_from_bits(const DevGraph& g, const Lds& L,
                                                const uint32_t* bits, uint8_t* corr, uint8_t* flips) {
   if (threadIdx.x < 4) L.u32(kOffFlips)[threadIdx.x] = 0u;
-  __syncthreads();
+  lds_barrier();
   unsigned long long f = 0;
   for (int j = threadIdx.x; j < g.n; j += blockDim.x) {
     const uint32_t b = (bits[j >> 5] >> (j & 31)) & 1u;
@@ -723,7 +795,8 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   const uint32_t t0 = dev_clock();
   RunRegs<CPT> rg;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + shot * g.m,
-                                    a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error);
+                                    a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
+                                    &a.fi);
   nruns += 1;
   niters += rr.iters;
   if (rr.conv || a.max_rounds == 0) {
@@ -899,7 +972,8 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       box[2] = (int)(shot & 0xFFFFFFFF);
       box[3] = (int)(shot >> 32);
     }
-    __syncthreads();
+    // LDS only: the previous step's output stores may still be in flight.
+    lds_barrier();
     const int kind = box[0];
     const uint32_t item = (uint32_t)box[1];
     const long long shot = (long long)(uint32_t)box[2] | ((long long)box[3] << 32);

@@ -70,6 +70,13 @@ struct bsd_code_s {
   size_t lds = 0;
   std::vector<void*> owned;  // device buffers of the graph
   std::vector<int32_t> colptr, rowidx;
+  std::vector<float> lam_host;        // prior LLRs as uploaded
+  std::vector<uint32_t> cedge_host;   // LDS position | rank << 16, CSC order
+  // First-iteration tables (for one alpha at a time).
+  FirstIter fi{};
+  float fi_alpha = 0.f;
+  bool fi_valid = false;
+  float* d_d0 = nullptr;
   // Batched workspace (grown on demand).
   int ws_bw = 0;
   int nctx = 0;
@@ -350,13 +357,68 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
   return BSD_OK;
 }
 
+// Check phase of iteration 1 from the priors for a zero syndrome (eq. (1)
+// with E(0) = Lambda), in LDS edge order and in the kernels' single-precision
+// operations: least and second least magnitude of the row, alpha times the
+// one that excludes the edge, clamped to the message bound, signed by the
+// product of the other edges' signs.
+bsd_status ensure_first(bsd_code c, float alpha) {
+  if (c->fi_valid && c->fi_alpha == alpha) return BSD_OK;
+  const DevGraph& g = c->g;
+  const int n = g.n, m = g.m, nnz = g.nnz;
+  const std::vector<int32_t>& cp = c->colptr;
+  const std::vector<int32_t>& ri = c->rowidx;
+  const std::vector<float>& lam = c->lam_host;
+  std::vector<int> ecol(nnz);
+  for (int j = 0; j < n; ++j)
+    for (int e = cp[j]; e < cp[j + 1]; ++e) ecol[e] = j;
+  std::vector<std::vector<int>> rows(m);
+  for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);
+  std::vector<float> d0((size_t)g.nnz_pad, 0.f);
+  for (int i = 0; i < m; ++i) {
+    float m1 = kLlrMax, m2 = kLlrMax;
+    bool par = false;
+    for (int e : rows[i]) {
+      const float v = lam[ecol[e]], a = std::fabs(v);
+      par ^= std::signbit(v);
+      m2 = std::max(m1, std::min(m2, a));
+      m1 = std::min(m1, a);
+    }
+    const float d1 = std::fmin(alpha * m1, kLlrMax), d2 = std::fmin(alpha * m2, kLlrMax);
+    for (int e : rows[i]) {
+      const float v = lam[ecol[e]];
+      const float mag = std::fabs(v) == m1 ? d2 : d1;
+      d0[c->cedge_host[e] & 0xFFFFu] = (par ^ std::signbit(v)) ? -mag : mag;
+    }
+  }
+  if (!c->d_d0) {
+    if (hipMalloc((void**)&c->d_d0, (size_t)g.nnz_pad * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot allocate the first-iteration table");
+    }
+  }
+  HIP_OR_FAIL(hipMemcpy(c->d_d0, d0.data(), (size_t)g.nnz_pad * 4, hipMemcpyHostToDevice));
+  c->fi.d0 = c->d_d0;
+  c->fi.enabled = 1;
+  c->fi_alpha = alpha;
+  c->fi_valid = true;
+  drop_graph(c);
+  return BSD_OK;
+}
+
 bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
                           uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
                           bsd_stats* stats, uint32_t* lat) {
   bsd_status st = ensure_batched(c, p->beam_width);
   if (st != BSD_OK) return st;
+  const bool table = !(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1;
+  if (table) {
+    st = ensure_first(c, p->alpha);
+    if (st != BSD_OK) return st;
+  }
   BatchArgs a{};
   a.g = c->g;
+  if (table) a.fi = c->fi;
   a.shots = shots;
   a.syn = syn;
   a.corr = corr;
@@ -551,6 +613,8 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   g.maxdeg_row = maxdeg;
   c->colptr.assign(h_colptr, h_colptr + n + 1);
   c->rowidx.assign(h_rowidx, h_rowidx + nnz);
+  c->lam_host = lam;
+  c->cedge_host = cedge;
   int32_t* d_diag;
   uint16_t* d_ror;
   uint8_t* d_dor;
@@ -621,6 +685,7 @@ bsd_status bsd_code_destroy(bsd_code c) {
   if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  hipFree(c->d_d0);
   free_workspace(c);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);

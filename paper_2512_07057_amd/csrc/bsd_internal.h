@@ -91,8 +91,18 @@ struct BatchState {
   Ring ctxq;
 };
 
+// The check phase of iteration 1 in a run from the priors with no masked
+// node depends on the syndrome only through the signs (-1)^{s_i} of eq. (1),
+// since E(0) = Lambda for every shot.  d0 holds D(1) for s = 0 in LDS edge
+// order, formed with the same single-precision operations as the kernels.
+struct FirstIter {
+  const float* d0;  // [nnz_pad] LDS order
+  int32_t enabled;
+};
+
 struct BatchArgs {
   DevGraph g;
+  FirstIter fi;
   long long shots;
   const uint8_t* syn;
   uint8_t* corr;

@@ -67,3 +67,23 @@ def test_autotune_keeps_results(bsd, key, wl, shots):
     after = _np(code.decode(syn, prm))
     for k in before:
         np.testing.assert_array_equal(after[k], before[k])
+
+
+@pytest.mark.parametrize("wl,hot,shots", [("W2", 0, 20000), ("W2", 40, 12), ("W1", 0, 2000),
+                                          ("W0", 0, 2000)])
+def test_first_iteration_table_equals_dense(bsd, wl, hot, shots):
+    """Iteration 1 of the initial runs taken from the per-(code, alpha) table
+    (default) gives the same outputs and work counts as eq. (1) computed in
+    full."""
+    W = workloads.WORKLOADS[wl]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    syn = torch.from_numpy(gc.samples(wl, shots, seed=21, hot=hot)["syndromes"]).cuda()
+    P = W.params
+    dense = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round, 1,
+                            P.alpha, bsd.MODE_BATCHED, bsd.FLAG_DENSE_FIRST)
+    a = code.decode(syn, dense)
+    b = code.decode(syn, gc.params_for(bsd, P))
+    for k in ("corrections", "flips", "converged"):
+        np.testing.assert_array_equal(a[k].cpu().numpy(), b[k].cpu().numpy())
+    assert a["stats"]["deep_shots"] == b["stats"]["deep_shots"]
+    gc.log(wl, hot, "dense ms", a["stats"]["kernel_ms"], "table ms", b["stats"]["kernel_ms"])
