@@ -107,7 +107,7 @@ typedef struct {
  * Limits: m <= 2048, n <= 16384, k <= 64, column degree <= 8, row degree
  * <= 252, and the fp32 edge messages of one BP run (4 * nnz bytes plus
  * about 7 KB of per-run state) must fit in the 160 KB LDS of one compute
- * unit (nnz <= 39100).
+ * unit (nnz <= 39150).
  * Errors: BSD_EINVAL for malformed CSC, p outside (0,1) or limits exceeded;
  * BSD_ENOMEM, BSD_EDEVICE. */
 bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_colptr,

@@ -50,7 +50,7 @@ constexpr int kOffOrder = kOffAminj + 64;            // int32[128] rank of each 
 constexpr int kOffByrank = kOffOrder + 512;          // int32[128] child of each rank
 constexpr int kOffMark = kOffByrank + 512;           // int32[196]
 constexpr int kOffNewslots = kOffMark + 784;         // int32[192]
-constexpr int kOffMsg = kOffNewslots + 768;          // float[nnz_pad + 64]
+constexpr int kOffMsg = kOffNewslots + 768;          // float[nnz_pad + kTrashWords + 4]
 static_assert(kOffMsg % 16 == 0, "message area must be 16-byte aligned");
 
 struct Lds {
@@ -66,10 +66,10 @@ struct Lds {
   __device__ __forceinline__ uint32_t* resid(int b) const { return u32(kOffResid + 256 * b); }
 };
 
-// After the messages: 64 trash words (stores of absent edges), then one word
-// that stays 0.0 (loads of absent edges).
+// After the messages: one trash word per lane that takes stores of absent
+// edges (never read), then one word that stays 0.0 (loads of absent edges).
 __host__ __device__ inline size_t lds_need(const DevGraph& g) {
-  return (size_t)kOffMsg + ((size_t)g.nnz_pad + 68) * 4;
+  return (size_t)kOffMsg + ((size_t)g.nnz_pad + kTrashWords + 4) * 4;
 }
 
 // Barrier for LDS data only: waits for this wave's LDS operations, not for
@@ -152,7 +152,9 @@ __device__ __forceinline__ uint32_t trash_pos(const DevGraph& g) {
   return (uint32_t)g.nnz_pad + (threadIdx.x & 63u);
 }
 
-__device__ __forceinline__ uint32_t zero_pos(const DevGraph& g) { return (uint32_t)g.nnz_pad + 64u; }
+__device__ __forceinline__ uint32_t zero_pos(const DevGraph& g) {
+  return (uint32_t)g.nnz_pad + kTrashWords;
+}
 
 
 // Load a lane's graph data (called by every thread, before any run).
@@ -230,7 +232,7 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
   const int kmax = __builtin_amdgcn_readfirstlane(dg);
   if (kmax == 0) return;
   const int kmin = __builtin_amdgcn_readlane(dg, 63);
-  const uint32_t tp = trash_pos(g), zp = zero_pos(g);
+  const uint32_t zp = zero_pos(g);
   uint32_t sgn = dg ? ((L.sprime()[r >> 5] >> (r & 31)) & 1u) << 31 : 0u;
   float m1 = kLlrMax, m2 = kLlrMax;
   int k = 0;
@@ -261,17 +263,19 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
     for (int u = 0; u < 4; ++u) msg[pp[u]] = check_out<MASKED>(vv[u], sgn, m1, d1, d2);
   }
   for (; k < kmax; ++k) {
-    const bool ok = k < dg;
-    const uint32_t p = ok ? (uint32_t)(diag[k] + r) : tp;
-    msg[p] = check_out<MASKED>(msg[p], sgn, m1, d1, d2);
+    if (k < dg) {
+      const uint32_t p = (uint32_t)(diag[k] + r);
+      msg[p] = check_out<MASKED>(msg[p], sgn, m1, d1, d2);
+    }
   }
 }
 
 // Eqs. (2)-(4) for one column with at most D edges (D uniform over the wave).
+// Absent edges read the zero word; their stores, and all stores of inactive
+// lanes (masked nodes, columns past n), go to the lane's trash word.
 template <int D, int CPT, int PW>
-__device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_t* resid,
-                                        const Res<CPT, PW>& R, int c, bool active, float& sl,
-                                        uint32_t& eb) {
+__device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
+                                        int c, bool active, float& sl, uint32_t& eb) {
   float* msg = L.msg();
   uint32_t dw = R.deg[c >> 3];
   asm volatile("" : "+v"(dw));
@@ -288,7 +292,7 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_
     asm volatile("" : "+v"(pk[w]));
   }
 #pragma unroll
-  for (int e = 0; e < D; ++e) {  // absent edges read the zero word and write the trash word
+  for (int e = 0; e < D; ++e) {
     p[e] = (pk[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
     d[e] = msg[p[e]];
     p[e] = (active && e < dg) ? p[e] : tp;
@@ -305,12 +309,20 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, uint32_
   const float post = pre;  // eq. (3)
   sl = active ? sl + post : sl;
   eb = (active && post <= 0.f) ? 1u : 0u;  // eq. (4)
-  if (eb) {
-    const int j = c * (int)blockDim.x + (int)threadIdx.x;
-    const int st = (int)(g.colinfo[j] & 0xFFFFFFu);
-    for (int e = 0; e < dg; ++e) {
-      const uint32_t rk = g.cedge[st + e] >> 16;
-      atomicXor(&resid[rk >> 5], 1u << (rk & 31));
+}
+
+// The syndrome residual s' + H e-hat: each set hard decision flips the bits
+// of its column's detectors.  Done after all columns so that a wave waits
+// for one round of rank-table loads.
+__device__ __forceinline__ void flip_resid(const DevGraph& g, uint32_t* resid, uint32_t ebits) {
+  for (uint32_t mk = ebits; mk; mk &= mk - 1u) {
+    const int c = __builtin_ctz(mk);
+    const uint4 rq = g.crank[c * (int)blockDim.x + (int)threadIdx.x];
+    const uint32_t rw[4] = {rq.x, rq.y, rq.z, rq.w};
+#pragma unroll
+    for (int e = 0; e < kMaxDv; ++e) {
+      const uint32_t rk = (rw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+      if (rk != 0xFFFFu) atomicXor(&resid[rk >> 5], 1u << (rk & 31));
     }
   }
 }
@@ -326,18 +338,19 @@ __device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint3
     uint32_t eb = 0;
     const int D = col_dmax(R, c);
     switch (D) {
-      case 1: var_col<1>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 2: var_col<2>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 3: if constexpr (PW >= 2) var_col<3>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 4: if constexpr (PW >= 2) var_col<4>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 5: if constexpr (PW >= 3) var_col<5>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 6: if constexpr (PW >= 3) var_col<6>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 7: if constexpr (PW >= 4) var_col<7>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
-      case 8: if constexpr (PW >= 4) var_col<8>(g, L, resid, R, c, active, rg.sumllr[c], eb); break;
+      case 1: var_col<1>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 2: var_col<2>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 3: if constexpr (PW >= 2) var_col<3>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 4: if constexpr (PW >= 2) var_col<4>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 5: if constexpr (PW >= 3) var_col<5>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 6: if constexpr (PW >= 3) var_col<6>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 7: if constexpr (PW >= 4) var_col<7>(g, L, R, c, active, rg.sumllr[c], eb); break;
+      case 8: if constexpr (PW >= 4) var_col<8>(g, L, R, c, active, rg.sumllr[c], eb); break;
       default: break;
     }
     rg.ebits = (rg.ebits & ~(1u << c)) | (eb << c);
   }
+  flip_resid(g, resid, rg.ebits);
 }
 
 // One masked BP run (Algorithm 2).  The caller has placed `npairs` packed
@@ -345,18 +358,18 @@ __device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint3
 // `parent_csc` (CSC order), else from the priors.  When `cancel` is given the
 // run stops early once *cancel < my_gen (a lower generation converged).
 //
-// A run from the priors with no masked node and `fi` enabled takes the check
-// phase of iteration 1 from the table fi->d0: with E(0) = Lambda on every
-// edge, eq. (1) at t = 1 depends on the syndrome only through the factor
-// (-1)^{s_i}, so D(1) is the s = 0 value with its sign flipped on the rows of
-// flipped detectors.  The table holds that value bit for bit as check_rows
-// would form it.
+// A run from the priors with no masked node and `fi` enabled writes the
+// check phase of iteration 1 from the per-row table fi->rows: with E(0) =
+// Lambda on every edge, eq. (1) at t = 1 depends on the syndrome only through
+// the factor (-1)^{s_i}.  The values are bit for bit those check_rows would
+// form.
 template <int CPT, int PW>
-__device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
+__device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CPT, PW>& R,
                                          const float* parent, const float* parent_csc, int npairs,
                                          const uint8_t* syn, int T, bool stop, float alpha,
                                          const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
-                                         uint32_t* err, const FirstIter* fi = nullptr) {
+                                         uint32_t* err, const FirstIter* fi = nullptr,
+                                         bool have_pf = false, uint32_t pf = 0u) {
   const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
   const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
@@ -373,11 +386,17 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
   // s by row rank, 64 ranks per wave ballot.  A table run also fills the
   // residual of iteration 1 here (s' = s without masked nodes).
   uint32_t sbit[2];
+  uint4 rt[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    rt[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (table && (R.row[q] >> 31)) rt[q] = fi->rows[q * B + tid];
+  }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     uint32_t bit = 0;
     if (R.row[q] >> 31) {
-      const uint32_t b = syn[R.row[q] & 0xFFFFu];
+      const uint32_t b = have_pf ? (pf >> (8 * q)) & 0xFFu : syn[R.row[q] & 0xFFFFu];
       if (b > 1u) atomicOr(err, 1u);
       bit = b & 1u;
     }
@@ -394,28 +413,34 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
     }
   }
   if (table) {
-    // D(1) for the rows of this thread: table value, sign flipped where s_i = 1.
-    const uint32_t* d0 = reinterpret_cast<const uint32_t*>(fi->d0);
+    // D(1) on the edges of this thread's rows: magnitude y on the edge of the
+    // least |Lambda|, x elsewhere; sign (-1)^{s_i} times the parity of the
+    // other edges' priors.
     const int32_t* diag = L.i32(kOffDiag);
     uint32_t* mu = L.msgu();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int r = q * B + tid;
       const int dg = (int)((R.row[q] >> 16) & 0xFFu);
-      const uint32_t fl = sbit[q] << 31;
-      int k = 0;
-      for (; k + 4 <= dg; k += 4) {
-        const int4 dd = *reinterpret_cast<const int4*>(diag + k);
-        const int pp[4] = {dd.x + r, dd.y + r, dd.z + r, dd.w + r};
-        uint32_t vv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) vv[u] = d0[pp[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) mu[pp[u]] = vv[u] ^ fl;
-      }
-      for (; k < dg; ++k) {
-        const int pq = diag[k] + r;
-        mu[pq] = d0[pq] ^ fl;
+      const uint32_t x = rt[q].x, y = rt[q].y, info = rt[q].z;
+      const int argk = (int)(info & 0xFFu);
+      const uint32_t sg = (((info >> 8) & 1u) ^ sbit[q]) << 31;
+      if ((info >> 9) & 1u) {  // some prior of the row is negative
+        for (int k = 0; k < dg; ++k) {
+          const int pq = diag[k] + r;
+          const uint32_t nb = ((fi->negbits[pq >> 5] >> (pq & 31)) & 1u) << 31;
+          mu[pq] = (k == argk ? y : x) | (sg ^ nb);
+        }
+      } else {
+        int k = 0;
+        for (; k + 4 <= dg; k += 4) {
+          const int4 dd = *reinterpret_cast<const int4*>(diag + k);
+          mu[dd.x + r] = (k == argk ? y : x) | sg;
+          mu[dd.y + r] = (k + 1 == argk ? y : x) | sg;
+          mu[dd.z + r] = (k + 2 == argk ? y : x) | sg;
+          mu[dd.w + r] = (k + 3 == argk ? y : x) | sg;
+        }
+        for (; k < dg; ++k) mu[diag[k] + r] = (k == argk ? y : x) | sg;
       }
     }
   } else if (parent) {
@@ -439,7 +464,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   // Masked nodes leave every check (+inf) and fold their value into s'.
   if (npairs) {
 #pragma unroll
@@ -457,7 +482,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   RunRes rr{0, 0, 0};
@@ -472,7 +497,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
 #pragma unroll
         for (int q = 0; q < 2; ++q) check_rows<false>(g, L, R.row[q], q * B + tid, alpha);
       }
-      __syncthreads();
+      lds_barrier();
     }
     var_phase<CPT, PW>(g, L, resid, R, rg);
     if (tid == 0) {
@@ -480,7 +505,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, const 
       if (cancel) cx = __hip_atomic_load(cancel, __ATOMIC_RELAXED, AGENT) < my_gen;
       L.misc()[0] = cx;
     }
-    __syncthreads();
+    lds_barrier();
     uint32_t any = 0;
     for (int w = 0; w < g.words_m; w += 2) {
       const uint2 x = *reinterpret_cast<const uint2*>(resid + w);
@@ -608,19 +633,37 @@ __device__ __forceinline__ void flip_write(const DevGraph& g, const Lds& L, uint
 }
 
 // Shot output from register-resident hard decisions (columns c*B + tid).
-template <int CPT>
+// Also issues the loads the next step needs: the syndrome bits of the next
+// shot this workgroup starts and the length of the work queue.
+template <int CPT, int PW>
 __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, uint32_t bits,
-                                               uint8_t* corr, uint8_t* flips) {
+                                               uint8_t* corr, uint8_t* flips, const BatchArgs& a,
+                                               const Res<CPT, PW>& R, long long next_shot,
+                                               long long& pf_shot, uint32_t& pf, int& work_hint) {
   const int B = blockDim.x;
   unsigned long long f = 0;
+  // All loads before the stores: a wait for a load also waits for the
+  // stores issued before it.
+  if (threadIdx.x == 0) work_hint = __hip_atomic_load(&a.st->work.count, __ATOMIC_RELAXED, AGENT);
+  if (next_shot >= 0) {
+    const uint8_t* ns = a.syn + next_shot * g.m;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (R.row[q] >> 31) v |= (uint32_t)ns[R.row[q] & 0xFFFFu] << (8 * q);
+    pf = v;
+    pf_shot = next_shot;
+  }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int j = c * B + threadIdx.x;
-    if (j < g.n) {
-      const uint32_t b = (bits >> c) & 1u;
-      corr[j] = (uint8_t)b;
-      if (b) f ^= g.lmask[j];
-    }
+    if (j < g.n && ((bits >> c) & 1u)) f ^= g.lmask[j];
+  }
+  asm volatile("" ::: "memory");  // keep the order of issue
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + threadIdx.x;
+    if (j < g.n) corr[j] = (uint8_t)((bits >> c) & 1u);
   }
   flip_fold(L, f);
   flip_write(g, L, flips);
@@ -789,18 +832,26 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
 // return value tells whether the shot went deep and consumed it.
 template <int CPT, int PW>
 __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
-                                             const Res<CPT, PW>& R, long long shot, int ctx,
-                                             unsigned long long& nruns, unsigned long long& niters) {
+                                             Res<CPT, PW>& R, long long shot, int ctx,
+                                             unsigned long long& nruns, unsigned long long& niters,
+                                             int& work_hint, long long next_shot, long long& pf_shot,
+                                             uint32_t& pf) {
   const DevGraph& g = a.g;
-  const uint32_t t0 = dev_clock();
+  // The clock is read only when latencies are asked for, by one wave: the
+  // read returns on the same counter as LDS operations.
+  const uint32_t t0 = (a.lat && threadIdx.x < 64) ? dev_clock() : 0u;
   RunRegs<CPT> rg;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + shot * g.m,
                                     a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
-                                    &a.fi);
+                                    &a.fi, pf_shot == shot, pf);
+  pf_shot = -1;
   nruns += 1;
   niters += rr.iters;
   if (rr.conv || a.max_rounds == 0) {
-    emit_from_regs<CPT>(g, L, rg.ebits, a.corr + shot * g.n, a.flips + shot * g.k);
+    // Read the work queue's length now: the load completes while the shot is
+    // written out, and the next scheduling step skips the queue when empty.
+    emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + shot * g.n, a.flips + shot * g.k, a, R,
+                        next_shot, pf_shot, pf, work_hint);
     if (threadIdx.x == 0) {
       a.conv[shot] = (uint8_t)rr.conv;
       if (a.lat) a.lat[shot] = dev_clock() - t0;
@@ -839,7 +890,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
 
 template <int CPT, int PW>
 __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
-                                              const Res<CPT, PW>& R, uint32_t item,
+                                              Res<CPT, PW>& R, uint32_t item,
                                               unsigned long long& nruns,
                                               unsigned long long& niters) {
   const DevGraph& g = a.g;
@@ -931,15 +982,20 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   int spare = -1;                 // thread 0 only
   long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
   bool exhausted = false;         // thread 0 only
+  int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
+  long long pf_shot = -1;         // shot whose syndrome bits `pf` holds (uniform)
+  uint32_t pf = 0;
   int32_t* misc = L.misc();
   for (int it = 0;; ++it) {
     opaque_res<CPT, PW>(R);
-    int32_t* box = misc + 20 + 4 * (it & 1);  // alternating slots: one barrier per step
+    int32_t* box = misc + 20 + 6 * (it & 1);  // alternating slots: one barrier per step
     if (tid == 0) {
       int kind = 0;
       uint32_t item = 0;
       long long shot = -1;
-      if (ring_pop(&a.st->work, a.work_ring, &item)) {
+      const bool try_work = work_hint != 0;
+      work_hint = -1;
+      if (try_work && ring_pop(&a.st->work, a.work_ring, &item)) {
         kind = 1;
       } else if (!exhausted) {
         if (spare < 0) {
@@ -958,6 +1014,13 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
             kind = 2;
             shot = cnext++;
             item = (uint32_t)spare;
+            if (cnext >= cend && !exhausted) {  // claim the next chunk now: its first shot is prefetched
+              const unsigned long long b = __hip_atomic_fetch_add(
+                  &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
+              cnext = (long long)b;
+              cend = (long long)b + kChunk < a.shots ? (long long)b + kChunk : a.shots;
+              if (cnext >= a.shots) exhausted = true;
+            }
           }
         }
       }
@@ -971,15 +1034,22 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       box[1] = (int)item;
       box[2] = (int)(shot & 0xFFFFFFFF);
       box[3] = (int)(shot >> 32);
+      const long long nx = (kind == 2 && cnext < cend) ? cnext : -1;
+      box[4] = (int)(nx & 0xFFFFFFFF);
+      box[5] = (int)(nx >> 32);
     }
     // LDS only: the previous step's output stores may still be in flight.
     lds_barrier();
     const int kind = box[0];
     const uint32_t item = (uint32_t)box[1];
     const long long shot = (long long)(uint32_t)box[2] | ((long long)box[3] << 32);
+    const long long next_shot = (long long)(uint32_t)box[4] | ((long long)box[5] << 32);
     if (kind == 3) break;
     if (kind == 2) {
-      if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters) && tid == 0) spare = -1;
+      if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters, work_hint, next_shot,
+                                pf_shot, pf) &&
+          tid == 0)
+        spare = -1;
     } else if (kind == 1) {
       process_child<CPT, PW>(a, L, R, item, nruns, niters);
     }

@@ -76,7 +76,8 @@ struct bsd_code_s {
   FirstIter fi{};
   float fi_alpha = 0.f;
   bool fi_valid = false;
-  float* d_d0 = nullptr;
+  uint4* d_rows = nullptr;
+  uint32_t* d_negbits = nullptr;
   // Batched workspace (grown on demand).
   int ws_bw = 0;
   int nctx = 0;
@@ -358,10 +359,11 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
 }
 
 // Check phase of iteration 1 from the priors for a zero syndrome (eq. (1)
-// with E(0) = Lambda), in LDS edge order and in the kernels' single-precision
-// operations: least and second least magnitude of the row, alpha times the
-// one that excludes the edge, clamped to the message bound, signed by the
-// product of the other edges' signs.
+// with E(0) = Lambda), per detector rank, in the kernels' single-precision
+// operations: least and second least magnitude of the row, alpha times each,
+// clamped to the message bound; the diagonal index of the least (the first
+// in column order: on a tie both values are equal); the parity of the row's
+// negative priors.
 bsd_status ensure_first(bsd_code c, float alpha) {
   if (c->fi_valid && c->fi_alpha == alpha) return BSD_OK;
   const DevGraph& g = c->g;
@@ -373,32 +375,45 @@ bsd_status ensure_first(bsd_code c, float alpha) {
   for (int j = 0; j < n; ++j)
     for (int e = cp[j]; e < cp[j + 1]; ++e) ecol[e] = j;
   std::vector<std::vector<int>> rows(m);
-  for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);
-  std::vector<float> d0((size_t)g.nnz_pad, 0.f);
+  for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);  // ascending column = diagonal order
+  std::vector<uint4> rt((size_t)m);
+  std::vector<uint32_t> neg((size_t)g.nnz_pad / 32 + 1, 0u);
   for (int i = 0; i < m; ++i) {
     float m1 = kLlrMax, m2 = kLlrMax;
-    bool par = false;
+    bool par = false, anyneg = false;
+    int argk = 0, kk = 0;
     for (int e : rows[i]) {
       const float v = lam[ecol[e]], a = std::fabs(v);
       par ^= std::signbit(v);
+      anyneg |= std::signbit(v);
+      if (std::signbit(v)) {
+        const uint32_t pos = c->cedge_host[e] & 0xFFFFu;
+        neg[pos >> 5] |= 1u << (pos & 31);
+      }
+      if (a < m1) argk = kk;
       m2 = std::max(m1, std::min(m2, a));
       m1 = std::min(m1, a);
+      ++kk;
     }
-    const float d1 = std::fmin(alpha * m1, kLlrMax), d2 = std::fmin(alpha * m2, kLlrMax);
-    for (int e : rows[i]) {
-      const float v = lam[ecol[e]];
-      const float mag = std::fabs(v) == m1 ? d2 : d1;
-      d0[c->cedge_host[e] & 0xFFFFu] = (par ^ std::signbit(v)) ? -mag : mag;
-    }
+    const float x = std::fmin(alpha * m1, kLlrMax), y = std::fmin(alpha * m2, kLlrMax);
+    const uint32_t rank = rows[i].empty() ? 0u : (c->cedge_host[rows[i][0]] >> 16);
+    if (rows[i].empty()) continue;
+    uint32_t xb, yb;
+    std::memcpy(&xb, &x, 4);
+    std::memcpy(&yb, &y, 4);
+    rt[rank] = make_uint4(xb, yb, (uint32_t)argk | ((uint32_t)par << 8) | ((uint32_t)anyneg << 9), 0u);
   }
-  if (!c->d_d0) {
-    if (hipMalloc((void**)&c->d_d0, (size_t)g.nnz_pad * 4) != hipSuccess) {
+  if (!c->d_rows) {
+    if (hipMalloc((void**)&c->d_rows, (size_t)m * sizeof(uint4)) != hipSuccess ||
+        hipMalloc((void**)&c->d_negbits, neg.size() * 4) != hipSuccess) {
       (void)hipGetLastError();
       return fail(BSD_ENOMEM, "cannot allocate the first-iteration table");
     }
   }
-  HIP_OR_FAIL(hipMemcpy(c->d_d0, d0.data(), (size_t)g.nnz_pad * 4, hipMemcpyHostToDevice));
-  c->fi.d0 = c->d_d0;
+  HIP_OR_FAIL(hipMemcpy(c->d_rows, rt.data(), (size_t)m * sizeof(uint4), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipMemcpy(c->d_negbits, neg.data(), neg.size() * 4, hipMemcpyHostToDevice));
+  c->fi.rows = c->d_rows;
+  c->fi.negbits = c->d_negbits;
   c->fi.enabled = 1;
   c->fi_alpha = alpha;
   c->fi_valid = true;
@@ -593,6 +608,10 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
       cedge[e] = (uint32_t)pos | ((uint32_t)rank_of_row[i] << 16);
     }
   }
+  std::vector<uint16_t> crank((size_t)n * 8, 0xFFFFu);  // 0xFFFF: no edge
+  for (int j = 0; j < n; ++j)
+    for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e)
+      crank[(size_t)j * 8 + (e - h_colptr[j])] = (uint16_t)(cedge[e] >> 16);
   std::vector<float> lam(n);
   for (int j = 0; j < n; ++j) lam[j] = (float)std::log((1.0 - p[j]) / p[j]);
   std::vector<uint64_t> lmask(n, 0);
@@ -619,29 +638,31 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   uint16_t* d_ror;
   uint8_t* d_dor;
   uint32_t *d_ci, *d_ce;
+  uint16_t* d_cr;
   float* d_lam;
   uint64_t* d_lm;
   if (dev_upload(&d_diag, diag_ptr) != hipSuccess || dev_upload(&d_ror, row_of_rank) != hipSuccess ||
       dev_upload(&d_dor, deg_of_rank) != hipSuccess || dev_upload(&d_ci, colinfo) != hipSuccess ||
-      dev_upload(&d_ce, cedge) != hipSuccess || dev_upload(&d_lam, lam) != hipSuccess ||
-      dev_upload(&d_lm, lmask) != hipSuccess) {
+      dev_upload(&d_ce, cedge) != hipSuccess || dev_upload(&d_cr, crank) != hipSuccess ||
+      dev_upload(&d_lam, lam) != hipSuccess || dev_upload(&d_lm, lmask) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
-  c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_lam, d_lm};
+  c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_cr, d_lam, d_lm};
   g.diag_ptr = d_diag;
   g.row_of_rank = d_ror;
   g.deg_of_rank = d_dor;
   g.colinfo = d_ci;
   g.cedge = d_ce;
+  g.crank = reinterpret_cast<const uint4*>(d_cr);
   g.lambda = d_lam;
   g.lmask = d_lm;
 
   // Launch geometry: one BP run per workgroup; columns c * block + tid,
   // detector rows of rank q * block + tid (q < 2).
   c->lds = lds_bytes_for(g);
-  if (c->lds > (size_t)kLdsBytes || g.nnz_pad + 64 > 65535 || maxdeg > 252) {
+  if (c->lds > (size_t)kLdsBytes || g.nnz_pad + kTrashWords + 1 > 65535 || maxdeg > 252) {
     bsd_code_destroy(c);
     return fail(BSD_EINVAL, "graph too large: %d edges need %zu bytes of LDS (limit %d)", nnz,
                 c->lds, kLdsBytes);
@@ -685,7 +706,8 @@ bsd_status bsd_code_destroy(bsd_code c) {
   if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-  hipFree(c->d_d0);
+  hipFree(c->d_rows);
+  hipFree(c->d_negbits);
   free_workspace(c);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);

@@ -16,6 +16,7 @@ constexpr int kMaxWaves = 16;      // 1024 threads per workgroup at most
 constexpr int kMaxCpt = 32;        // columns per thread at most
 constexpr float kLlrMax = 1e30f;   // saturation of every message
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kTrashWords = 64;  // LDS trash words after the messages, one per lane
 
 // Device-resident Tanner graph.  Rows are renumbered by "rank" (descending
 // degree); the LDS message of the edge (row of rank r, k-th neighbour in
@@ -33,6 +34,7 @@ struct DevGraph {
   const uint8_t* deg_of_rank;  // [m]
   const uint32_t* colinfo;     // [n] first CSC edge (bits 0..23) | degree << 24
   const uint32_t* cedge;       // [nnz] CSC order: LDS position (bits 0..15) | row rank << 16
+  const uint4* crank;          // [n] row ranks of column j's edges, 16 bits each (8 slots, 0xFFFF unused)
   const float* lambda;         // [n] prior LLRs
   const uint64_t* lmask;       // [n] logical rows flipped by each column
 };
@@ -93,10 +95,15 @@ struct BatchState {
 
 // The check phase of iteration 1 in a run from the priors with no masked
 // node depends on the syndrome only through the signs (-1)^{s_i} of eq. (1),
-// since E(0) = Lambda for every shot.  d0 holds D(1) for s = 0 in LDS edge
-// order, formed with the same single-precision operations as the kernels.
+// since E(0) = Lambda for every shot.  Per detector rank the table holds what
+// eq. (1) needs for s = 0, formed with the kernels' single-precision
+// operations: x = alpha * least |Lambda| of the row and y = alpha * second
+// least (both clamped to the message bound), the diagonal index of the edge
+// holding the least (it receives y, every other edge x), and the parity of
+// the row's negative priors.
 struct FirstIter {
-  const float* d0;  // [nnz_pad] LDS order
+  const uint4* rows;        // [m] per rank: x bits, y bits, argk | parity << 8 | anyneg << 9, 0
+  const uint32_t* negbits;  // [nnz_pad / 32 + 1] LDS order: sign bit of Lambda of the edge's column
   int32_t enabled;
 };
 
