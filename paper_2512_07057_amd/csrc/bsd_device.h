@@ -609,6 +609,44 @@ __device__ __forceinline__ void store_bits(const DevGraph& g, uint32_t* dst, uin
   }
 }
 
+// wt(e-hat) = sum_j e_j log((1-p_j)/p_j) (Appendix B) in double precision,
+// summed in ascending column order, and a 64-bit digest of e-hat, by thread
+// 0 from an LDS bit-vector.  Every thread calls this; `bits` holds the hard
+// decisions of columns c*B + tid.
+template <int CPT>
+__device__ __forceinline__ void weight_hash(const DevGraph& g, const Lds& L, const double* lam64,
+                                            uint32_t bits, double* wt, uint64_t* hash) {
+  const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t* bm = L.u32(kOffRedf);  // words_n <= 512
+  lds_barrier();
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + tid;
+    const unsigned long long bal = __ballot(j < g.n && ((bits >> c) & 1u));
+    if (lane == 0) {
+      const int w = (c * B + wave * 64) >> 5;
+      if (w < g.words_n) bm[w] = (uint32_t)bal;
+      if (w + 1 < g.words_n) bm[w + 1] = (uint32_t)(bal >> 32);
+    }
+  }
+  lds_barrier();
+  if (tid == 0) {
+    double s = 0.0;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int w = 0; w < g.words_n; ++w) {
+      uint32_t x = bm[w];
+      h = (h ^ x) * 0x100000001b3ull;
+      while (x) {
+        s += lam64[w * 32 + __builtin_ctz(x)];
+        x &= x - 1u;
+      }
+    }
+    *wt = s;
+    *hash = h;
+  }
+  lds_barrier();
+}
+
 __device__ __forceinline__ void store_msg(const DevGraph& g, const Lds& L, float* dst) {
   const float4* src = reinterpret_cast<const float4*>(L.msg());
   float4* d = reinterpret_cast<float4*>(dst);
@@ -734,6 +772,22 @@ __device__ __forceinline__ void finish_deep(const BatchArgs& a, const Lds& L, in
   }
 }
 
+// Output the lightest result (least wt; the first found among equals).
+__device__ __forceinline__ void finish_lightest(const BatchArgs& a, const Lds& L, int ctx,
+                                                long long shot, int nres, uint32_t t_start) {
+  const Ctx* C = a.ctxs + ctx;
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int r = 1; r < nres; ++r)
+      if (C->res_wt[r] < C->res_wt[best]) best = r;
+    L.misc()[18] = best;
+  }
+  __syncthreads();
+  const int best = L.misc()[18];
+  const uint32_t* bits = a.results + ((size_t)ctx * a.num_results + best) * a.g.words_n;
+  finish_deep(a, L, ctx, shot, bits, 1, t_start);
+}
+
 // Selection at the end of a round (Algorithm 3 with Appendix B), run by the
 // workgroup that finished the round's last child.
 __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, int ctx) {
@@ -751,6 +805,52 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
     const int s = C->slots[nset + best];
     finish_deep(a, L, ctx, shot, (const uint32_t*)(slot_ptr(a, ctx, s) + slot_ehat_off(g)), 1, t0);
     return;
+  }
+  int nres = C->nresults;
+  if (a.num_results > 1) {
+    // Converged children join the results in exploration order (generation),
+    // once each; the search ends when num_results distinct ones are found.
+    // Digests of the results so far are mirrored in LDS, so that every
+    // thread takes the same branches.
+    uint32_t* res0 = a.results + (size_t)ctx * a.num_results * g.words_n;
+    uint64_t* rh = reinterpret_cast<uint64_t*>(L.u32(kOffOrder));  // [kMaxResults]
+    for (int r = tid; r < nres; r += blockDim.x) rh[r] = C->res_hash[r];
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      if (C->parent_next_pos[c >> 1] < 0 || C->child_state[c] != 1) continue;
+      const uint32_t* cb = (const uint32_t*)(slot_ptr(a, ctx, C->slots[nset + c]) + slot_ehat_off(g));
+      const uint64_t h = C->child_hash[c];
+      bool dup = false;
+      for (int r = 0; r < nres && !dup; ++r) {
+        if (rh[r] != h) continue;
+        if (tid == 0) misc[17] = 0;
+        __syncthreads();
+        const uint32_t* rb = res0 + (size_t)r * g.words_n;
+        for (int w = tid; w < g.words_n; w += blockDim.x)
+          if (cb[w] != rb[w]) misc[17] = 1;
+        __syncthreads();
+        dup = misc[17] == 0;
+        __syncthreads();
+      }
+      if (dup) continue;
+      uint32_t* dst = res0 + (size_t)nres * g.words_n;
+      for (int w = tid; w < g.words_n; w += blockDim.x) dst[w] = cb[w];
+      if (tid == 0) {
+        C->res_wt[nres] = C->child_wt[c];
+        C->res_hash[nres] = h;
+        rh[nres] = h;
+      }
+      __syncthreads();
+      ++nres;
+      if (nres >= a.num_results) break;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) C->nresults = nres;
+    if (nres >= a.num_results) {
+      finish_lightest(a, L, ctx, shot, nres, t0);
+      return;
+    }
   }
   // Rank the children by (score desc, generation asc); children of parents
   // that could not branch do not exist.
@@ -786,6 +886,7 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
       for (int q = 0; q < ns; ++q) nbranch += C->child_next_pos[byrank[q]] >= 0;
       action = nbranch > 0 ? 0 : 2;
     }
+    if (action != 0 && nres > 0) action = 3;  // the search ends with results: the lightest
     misc[8] = action;
     misc[9] = ns > 0 ? C->slots[nset + byrank[0]] : 0;
     if (action == 0) {
@@ -820,7 +921,9 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
   const int action = misc[8];
   const int s0 = misc[9];
   __syncthreads();
-  if (action == 1) {
+  if (action == 3) {
+    finish_lightest(a, L, ctx, shot, nres, t0);
+  } else if (action == 1) {
     finish_deep(a, L, ctx, shot, (const uint32_t*)(slot_ptr(a, ctx, s0) + slot_ehat_off(g)), 0, t0);
   } else if (action == 2) {
     finish_deep(a, L, ctx, shot,
@@ -847,7 +950,8 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   pf_shot = -1;
   nruns += 1;
   niters += rr.iters;
-  if (rr.conv || a.max_rounds == 0) {
+  const bool many = a.num_results > 1;
+  if ((rr.conv && !many) || a.max_rounds == 0) {
     // Read the work queue's length now: the load completes while the shot is
     // written out, and the next scheduling step skips the queue when empty.
     emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + shot * g.n, a.flips + shot * g.k, a, R,
@@ -867,6 +971,10 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   char* seed = slot_ptr(a, ctx, 0);
   store_msg(g, L, (float*)seed);
   store_bits<CPT>(g, (uint32_t*)(slot_ptr(a, ctx, 3 * a.bw) + slot_ehat_off(g)), rg.ebits);
+  if (rr.conv) {  // num_results > 1: the initial solution is the first result
+    store_bits<CPT>(g, a.results + (size_t)ctx * a.num_results * g.words_n, rg.ebits);
+    weight_hash<CPT>(g, L, a.lam64, rg.ebits, &C->res_wt[0], &C->res_hash[0]);
+  }
   if (threadIdx.x == 0) {
     *(int32_t*)(seed + slot_pairs_off(g)) = 0;
     C->shot = (int32_t)shot;
@@ -874,7 +982,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     C->nset = 1;
     C->pending = 2;
     C->best_gen = 0x7FFFFFFF;
-    C->nresults = 0;
+    C->nresults = rr.conv ? 1 : 0;
     C->t_start = t0;
     C->parent_next_pos[0] = next_pos;
     __hip_atomic_fetch_add(&a.st->deep, 1ull, __ATOMIC_RELAXED, AGENT);
@@ -926,25 +1034,28 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
     if (tid == 0) *(int32_t*)(mslot + slot_pairs_off(g)) = np + 1;
     __syncthreads();
     RunRegs<CPT> rg;
+    const bool many = a.num_results > 1;  // converged children keep branching; no cancellation
     const RunRes rr = bp_run<CPT, PW>(g, L, R, (const float*)pslot, nullptr, np + 1,
                                       a.syn + shot * g.m, a.round_iters, true, a.alpha,
-                                      &C->best_gen, c, rg, &a.st->error);
+                                      many ? nullptr : &C->best_gen, c, rg, &a.st->error);
     nruns += 1;
     niters += rr.iters;
     uint32_t* mbitsv = (uint32_t*)(mslot + slot_ehat_off(g));
+    const uint32_t filled = (rg.ebits & ~rg.mbits) | rg.vbits;
     if (rr.cancelled) {
       state = 2;
-    } else if (rr.conv) {
+    } else if (rr.conv && !many) {
       state = 1;
-      store_bits<CPT>(g, mbitsv, (rg.ebits & ~rg.mbits) | rg.vbits);
+      store_bits<CPT>(g, mbitsv, filled);
       if (tid == 0) __hip_atomic_fetch_min(&C->best_gen, c, __ATOMIC_RELAXED, AGENT);
     } else {
-      state = 0;
+      state = rr.conv ? 1 : 0;
       float score;
       int next_pos;
       score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);
       store_msg(g, L, (float*)mslot);
-      store_bits<CPT>(g, mbitsv, (rg.ebits & ~rg.mbits) | rg.vbits);
+      store_bits<CPT>(g, mbitsv, filled);
+      if (rr.conv) weight_hash<CPT>(g, L, a.lam64, filled, &C->child_wt[c], &C->child_hash[c]);
       if (tid == 0) {
         C->child_score[c] = score;
         C->child_next_pos[c] = next_pos;
@@ -1077,7 +1188,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_single(SingleArgs a) {
   float score = 0.f;
   int next_pos = -1;
   if (a.want_score) score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);
-  if (a.out_msg && !rr.conv) store_msg(g, L, a.out_msg);
+  if (a.out_msg && (!rr.conv || a.keep_msg)) store_msg(g, L, a.out_msg);
   const uint32_t filled = (rg.ebits & ~rg.mbits) | rg.vbits;
   if (a.out_ehat_bits) store_bits<CPT>(g, a.out_ehat_bits, filled);
 #pragma unroll

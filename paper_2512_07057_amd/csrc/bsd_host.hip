@@ -71,6 +71,11 @@ struct bsd_code_s {
   std::vector<void*> owned;  // device buffers of the graph
   std::vector<int32_t> colptr, rowidx;
   std::vector<float> lam_host;        // prior LLRs as uploaded
+  std::vector<double> lam64_host;     // the same in double precision: wt(e) terms (Appendix B)
+  double* d_lam64 = nullptr;
+  uint32_t* d_results = nullptr;      // num_results > 1: per-context result bit-vectors
+  size_t results_words = 0;
+  uint32_t* d_resbits = nullptr;      // plain form: the chosen result's bits
   std::vector<uint32_t> cedge_host;   // LDS position | rank << 16, CSC order
   // First-iteration tables (for one alpha at a time).
   FirstIter fi{};
@@ -137,6 +142,9 @@ bsd_status ensure_batched(bsd_code c, int bw) {
   if (c->ws_bw >= bw && c->st && c->nctx >= c->grid + 64) return BSD_OK;
   drop_graph(c);
   free_workspace(c);
+  hipFree(c->d_results);
+  c->d_results = nullptr;
+  c->results_words = 0;
   const int nctx = c->grid + 64;
   const int per = 3 * bw + 1;
   c->slot_stride = slot_bytes(c->g);
@@ -163,6 +171,7 @@ bsd_status ensure_plain(bsd_code c, int bw) {
     if (hipMalloc((void**)&c->d_pairs, kMaxRounds * 4) != hipSuccess ||
         hipMalloc((void**)&c->d_result, 16) != hipSuccess ||
         hipMalloc((void**)&c->d_error, 4) != hipSuccess ||
+        hipMalloc((void**)&c->d_resbits, (size_t)c->g.words_n * 4) != hipSuccess ||
         hipHostMalloc((void**)&c->h_pinned, (kMaxRounds + 8) * 4, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       return fail(BSD_ENOMEM, "cannot allocate the single-run workspace");
@@ -192,8 +201,6 @@ bsd_status check_params(const bsd_code c, const bsd_params* p) {
     return fail(BSD_EINVAL, "iteration counts must be >= 0");
   if (p->num_results < 1 || p->num_results > kMaxResults)
     return fail(BSD_EINVAL, "num_results must be in [1, %d]", kMaxResults);
-  if (p->num_results != 1)
-    return fail(BSD_EINVAL, "num_results > 1 is not supported by the GPU path yet");
   if (!(p->alpha > 0.f) || !std::isfinite(p->alpha))
     return fail(BSD_EINVAL, "alpha must be positive and finite");
   if (p->mode != BSD_MODE_BATCHED && p->mode != BSD_MODE_PLAIN)
@@ -210,7 +217,7 @@ struct RunOut {
 // One BP run of the plain form: pairs up, launch, result down (synchronous).
 bsd_status plain_run(bsd_code c, hipStream_t s, const float* parent, const std::vector<int32_t>& pairs,
                      const uint8_t* syn, int T, float alpha, float* out_msg, uint32_t* out_bits,
-                     RunOut* r) {
+                     RunOut* r, bool keep_msg = false) {
   SingleArgs a{};
   a.g = c->g;
   a.parent = parent;
@@ -226,6 +233,7 @@ bsd_status plain_run(bsd_code c, hipStream_t s, const float* parent, const std::
   a.alpha = alpha;
   a.want_score = 1;
   a.out_msg = out_msg;
+  a.keep_msg = keep_msg ? 1 : 0;
   a.out_ehat_bits = out_bits;
   a.result = c->d_result;
   a.error = c->d_error;
@@ -256,11 +264,31 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
   if (st != BSD_OK) return st;
   HIP_OR_FAIL(hipMemsetAsync(c->d_error, 0, 4, s));
   const int bw = p->beam_width;
+  const int want = p->num_results;
+  const bool many = want > 1;  // converged runs keep their messages and keep branching
   auto slot = [&](int i) { return c->pslots + (size_t)i * c->slot_stride; };
   auto msg_of = [&](int i) { return (float*)slot(i); };
   auto bits_of = [&](int i) { return (uint32_t*)(slot(i) + slot_ehat_off(g)); };
   const int keeper = 3 * bw;
   int64_t runs = 0, iters = 0, deep = 0;
+  std::vector<std::vector<uint32_t>> res;  // num_results > 1: distinct solutions, in the order found
+  std::vector<double> res_wt;
+  std::vector<uint32_t> hb((size_t)g.words_n);
+  // Adds the solution in `slot` unless already found; true once `want` are found.
+  auto add_result = [&](int sl, bool* full) -> bsd_status {
+    HIP_OR_FAIL(hipMemcpyAsync(hb.data(), bits_of(sl), hb.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    *full = false;
+    for (const auto& r : res)
+      if (r == hb) return BSD_OK;
+    double w = 0.0;
+    for (int j = 0; j < g.n; ++j)
+      if ((hb[j >> 5] >> (j & 31)) & 1u) w += c->lam64_host[j];
+    res.push_back(hb);
+    res_wt.push_back(w);
+    *full = (int)res.size() >= want;
+    return BSD_OK;
+  };
   HIP_OR_FAIL(hipEventRecord(c->ev0, s));
   for (int64_t q = 0; q < shots; ++q) {
     const uint8_t* sq = syn + q * g.m;
@@ -269,18 +297,26 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
     e.corr = corr + q * g.n;
     e.flips = flips + q * g.k;
     e.conv = conv + q;
+    res.clear();
+    res_wt.clear();
     RunOut r0;
-    st = plain_run(c, s, nullptr, {}, sq, p->initial_iters, p->alpha, msg_of(0), bits_of(keeper), &r0);
+    st = plain_run(c, s, nullptr, {}, sq, p->initial_iters, p->alpha, msg_of(0), bits_of(keeper), &r0,
+                   many);
     if (st != BSD_OK) return st;
     ++runs;
     iters += r0.iters;
     int emit_slot = keeper, emit_conv = r0.conv;
-    if (!r0.conv && p->max_rounds > 0) {
+    bool emit_lightest = false;
+    if ((!r0.conv || many) && p->max_rounds > 0) {
       ++deep;
+      bool done = false;
+      if (r0.conv) {
+        st = add_result(keeper, &done);
+        if (st != BSD_OK) return st;
+      }
       std::vector<HostPath> set{{0, {}, r0.next_pos, 0.f, 0}};
       std::vector<int> free_slots;
       for (int i = 3 * bw - 1; i >= 1; --i) free_slots.push_back(i);
-      bool done = false;
       for (int rd = 1; rd <= p->max_rounds && !done; ++rd) {
         std::stable_sort(set.begin(), set.end(), [](const HostPath& a, const HostPath& b) {
           if (a.score != b.score) return a.score > b.score;
@@ -298,15 +334,25 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
             free_slots.pop_back();
             RunOut rr;
             st = plain_run(c, s, msg_of(set[k].slot), ch.pairs, sq, p->iters_per_round, p->alpha,
-                           msg_of(ch.slot), bits_of(ch.slot), &rr);
+                           msg_of(ch.slot), bits_of(ch.slot), &rr, many);
             if (st != BSD_OK) return st;
             ++runs;
             iters += rr.iters;
-            if (rr.conv) {
+            if (rr.conv && !many) {
               emit_slot = ch.slot;
               emit_conv = 1;
               done = true;
               break;
+            }
+            if (rr.conv) {
+              bool full = false;
+              st = add_result(ch.slot, &full);
+              if (st != BSD_OK) return st;
+              if (full) {
+                emit_lightest = true;
+                done = true;
+                break;
+              }
             }
             ch.next_pos = rr.next_pos;
             ch.score = rr.score;
@@ -322,23 +368,39 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
         for (size_t k = (size_t)bw; k < kids.size(); ++k) free_slots.push_back(kids[k].slot);
         if (kids.size() > (size_t)bw) kids.resize(bw);
         set = std::move(kids);
-        if (rd == p->max_rounds) {
-          emit_slot = set.empty() ? keeper : set[0].slot;
-          emit_conv = 0;
-        } else {
+        bool last = rd == p->max_rounds;
+        if (!last) {
           bool any = false;
           for (const HostPath& h : set) any |= h.next_pos >= 0;
-          if (!any) {
+          if (!any) {  // nothing can branch: the search ends with the initial decision
             emit_slot = keeper;
             emit_conv = 0;
-            break;
+            last = true;
           }
+        } else {
+          emit_slot = set.empty() ? keeper : set[0].slot;
+          emit_conv = 0;
+        }
+        if (last) {
+          emit_lightest = !res.empty();
+          break;
         }
       }
     }
-    e.ehat_bits = bits_of(emit_slot);
-    e.converged = emit_conv;
+    if (emit_lightest) {
+      size_t best = 0;
+      for (size_t r = 1; r < res.size(); ++r)
+        if (res_wt[r] < res_wt[best]) best = r;
+      HIP_OR_FAIL(hipMemcpyAsync(c->d_resbits, res[best].data(), res[best].size() * 4,
+                                 hipMemcpyHostToDevice, s));
+      e.ehat_bits = c->d_resbits;
+      e.converged = 1;
+    } else {
+      e.ehat_bits = bits_of(emit_slot);
+      e.converged = emit_conv;
+    }
     HIP_OR_FAIL(launch_emit(e, s));
+    if (emit_lightest) HIP_OR_FAIL(hipStreamSynchronize(s));  // res[best] is pageable host memory
   }
   HIP_OR_FAIL(hipEventRecord(c->ev1, s));
   uint32_t err = 0;
@@ -421,10 +483,28 @@ bsd_status ensure_first(bsd_code c, float alpha) {
   return BSD_OK;
 }
 
+// Result bit-vectors of every context for num_results > 1.
+bsd_status ensure_results(bsd_code c, int num_results) {
+  const size_t need = (size_t)c->nctx * num_results * c->g.words_n;
+  if (num_results <= 1 || c->results_words >= need) return BSD_OK;
+  drop_graph(c);
+  hipFree(c->d_results);
+  c->d_results = nullptr;
+  c->results_words = 0;
+  if (hipMalloc((void**)&c->d_results, need * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BSD_ENOMEM, "cannot allocate %zu bytes for num_results = %d", need * 4, num_results);
+  }
+  c->results_words = need;
+  return BSD_OK;
+}
+
 bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
                           uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
                           bsd_stats* stats, uint32_t* lat) {
   bsd_status st = ensure_batched(c, p->beam_width);
+  if (st != BSD_OK) return st;
+  st = ensure_results(c, p->num_results);
   if (st != BSD_OK) return st;
   const bool table = !(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1;
   if (table) {
@@ -446,6 +526,8 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.round_iters = p->iters_per_round;
   a.num_results = p->num_results;
   a.alpha = p->alpha;
+  a.lam64 = c->d_lam64;
+  a.results = c->d_results;
   a.st = c->st;
   a.work_ring = c->work_ring;
   a.work_cap = c->work_cap;
@@ -613,7 +695,9 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e)
       crank[(size_t)j * 8 + (e - h_colptr[j])] = (uint16_t)(cedge[e] >> 16);
   std::vector<float> lam(n);
-  for (int j = 0; j < n; ++j) lam[j] = (float)std::log((1.0 - p[j]) / p[j]);
+  std::vector<double> lam64(n);
+  for (int j = 0; j < n; ++j) lam64[j] = std::log((1.0 - p[j]) / p[j]);
+  for (int j = 0; j < n; ++j) lam[j] = (float)lam64[j];
   std::vector<uint64_t> lmask(n, 0);
   for (int j = 0; j < n && k > 0; ++j)
     for (int e = l_colptr[j]; e < l_colptr[j + 1]; ++e) lmask[j] ^= 1ull << l_rowidx[e];
@@ -633,23 +717,27 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   c->colptr.assign(h_colptr, h_colptr + n + 1);
   c->rowidx.assign(h_rowidx, h_rowidx + nnz);
   c->lam_host = lam;
+  c->lam64_host = lam64;
   c->cedge_host = cedge;
   int32_t* d_diag;
   uint16_t* d_ror;
   uint8_t* d_dor;
   uint32_t *d_ci, *d_ce;
   uint16_t* d_cr;
+  double* d_l64;
   float* d_lam;
   uint64_t* d_lm;
   if (dev_upload(&d_diag, diag_ptr) != hipSuccess || dev_upload(&d_ror, row_of_rank) != hipSuccess ||
       dev_upload(&d_dor, deg_of_rank) != hipSuccess || dev_upload(&d_ci, colinfo) != hipSuccess ||
       dev_upload(&d_ce, cedge) != hipSuccess || dev_upload(&d_cr, crank) != hipSuccess ||
-      dev_upload(&d_lam, lam) != hipSuccess || dev_upload(&d_lm, lmask) != hipSuccess) {
+      dev_upload(&d_lam, lam) != hipSuccess || dev_upload(&d_lm, lmask) != hipSuccess ||
+      dev_upload(&d_l64, lam64) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
-  c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_cr, d_lam, d_lm};
+  c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_cr, d_lam, d_lm, d_l64};
+  c->d_lam64 = d_l64;
   g.diag_ptr = d_diag;
   g.row_of_rank = d_ror;
   g.deg_of_rank = d_dor;
@@ -707,6 +795,8 @@ bsd_status bsd_code_destroy(bsd_code c) {
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   hipFree(c->d_rows);
+  hipFree(c->d_results);
+  hipFree(c->d_resbits);
   hipFree(c->d_negbits);
   free_workspace(c);
   for (void* p : c->owned) hipFree(p);

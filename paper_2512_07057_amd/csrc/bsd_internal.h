@@ -69,6 +69,10 @@ struct Ctx {
   float child_score[2 * kMaxBw];
   int32_t child_next_pos[2 * kMaxBw];
   int32_t child_state[2 * kMaxBw];    // 0 ran, 1 converged, 2 cancelled
+  double child_wt[2 * kMaxBw];        // converged children (num_results > 1): wt(e-hat)
+  uint64_t child_hash[2 * kMaxBw];    //   and a digest of e-hat
+  double res_wt[kMaxResults];         // results found so far, in the order found
+  uint64_t res_hash[kMaxResults];
   uint32_t init_ehat_off;             // unused padding kept for alignment
   int32_t pad1[3];
 };
@@ -110,6 +114,8 @@ struct FirstIter {
 struct BatchArgs {
   DevGraph g;
   FirstIter fi;
+  const double* lam64;    // [n] wt(e) contributions log((1-p_j)/p_j) in double precision
+  uint32_t* results;      // num_results > 1: [nctx][num_results][words_n] e-hat bits
   long long shots;
   const uint8_t* syn;
   uint8_t* corr;
@@ -142,7 +148,8 @@ struct SingleArgs {
   int32_t stop;
   float alpha;
   int32_t want_score;
-  float* out_msg;           // LDS order, written when not converged (or NULL)
+  float* out_msg;           // LDS order, written when not converged or keep_msg (or NULL)
+  int32_t keep_msg;
   float* out_csc;           // CSC order (or NULL)
   float* out_sumllr;        // [n] (or NULL)
   uint8_t* out_ehat;        // [n] bytes (or NULL)
