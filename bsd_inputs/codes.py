@@ -138,6 +138,33 @@ def bb_code_capacity(l: int, m: int, p: float, name: str | None = None) -> Probl
                               meta={"l": l, "m": m, "hz": hz})
 
 
+def bb_xyz(l: int, m: int, p: float, name: str | None = None) -> Problem:
+    """Depolarizing code-capacity problem of a BB code decoded over X, Y and Z
+    faults together.
+
+    Rows: the X checks (rows of H_X, which see Z and Y) then the Z checks (rows
+    of H_Z, which see X and Y).  Columns in three blocks [X faults | Z faults |
+    Y faults] of the data qubits; a Y column is the sum of the X and Z columns
+    of its qubit, which puts length-4 cycles into the Tanner graph.  Each
+    fault has probability p/3.  Logical rows: the Z-type logicals (they see the
+    X part of an error) then the X-type logicals (they see the Z part).
+    """
+    hx, hz = bb_matrices(l, m)
+    nq = hx.shape[1]
+    mx, mz = hx.shape[0], hz.shape[0]
+    zeros_x = np.zeros((mx, nq), np.uint8)
+    zeros_z = np.zeros((mz, nq), np.uint8)
+    h = np.vstack([np.hstack([zeros_x, hx, hx]),      # X checks: Z and Y faults
+                   np.hstack([hz, zeros_z, hz])])     # Z checks: X and Y faults
+    lz = x_logicals(hz, hx)   # ker(H_X) mod rowspace(H_Z): see X parts
+    lx = x_logicals(hx, hz)   # ker(H_Z) mod rowspace(H_X): see Z parts
+    L = np.vstack([np.hstack([lz, np.zeros_like(lz), lz]),
+                   np.hstack([np.zeros_like(lx), lx, lx])])
+    return problem_from_dense(name or f"bb{nq}_xyz", h, L, np.full(3 * nq, p / 3.0),
+                              meta={"l": l, "m": m, "kind": "xyz", "hx": hx, "hz": hz,
+                                    "qubits": nq})
+
+
 # --------------------------------------------------------------------------
 # Synthetic space-time graph of a BB code (stand-in for a circuit-level DEM)
 # --------------------------------------------------------------------------

@@ -67,6 +67,8 @@ WORKLOADS = {
     "W0": Workload("W0", "bb72_cc_p0.03", 10_000, 0, params_100iters(8)),
     "W1": Workload("W1", "bb144_cc_p0.05", 100_000, 0, params_100iters(32)),
     "W2": Workload("W2", "bb144_st12", 100_000, 0, TABLE_I["beam32_340iters"]),
+    # XYZ decoding of the [[144,12,12]] code under depolarizing noise
+    "W3": Workload("W3", "bb144_xyz_p0.06", 10_000, 0, params_100iters(8)),
 }
 
 _PROBLEM_CACHE: dict = {}
@@ -79,6 +81,10 @@ def problem(key: str) -> codes.Problem:
         pr = codes.bb_code_capacity(6, 6, 0.03, name=key)
     elif key == "bb144_cc_p0.05":
         pr = codes.bb_code_capacity(6, 12, 0.05, name=key)
+    elif key == "bb144_xyz_p0.06":
+        pr = codes.bb_xyz(6, 12, 0.06, name=key)
+    elif key == "bb72_xyz_p0.06":
+        pr = codes.bb_xyz(6, 6, 0.06, name=key)
     elif key == "bb144_st12":
         pr = codes.bb_spacetime(6, 12, rounds=12, hooks=6000, seed=0, name=key)
     else:

@@ -65,3 +65,39 @@ def test_syndromes_are_He():
     H = pr.dense_H()
     assert np.array_equal(d["syndromes"], (e.astype(int) @ H.T.astype(int)) % 2)
     assert np.array_equal(d["true_flips"], (e.astype(int) @ pr.L.T.astype(int)) % 2)
+
+
+@pytest.mark.parametrize("l,m", [(6, 6), (6, 12)])
+def test_xyz_problem_structure(l, m):
+    """Depolarizing XYZ problem: a Y fault is an X and a Z fault on the same
+    qubit; stabilizers are undetected and logically trivial; logical
+    operators are undetected and flip a logical row."""
+    pr = codes.bb_xyz(l, m, 0.06)
+    hx, hz = codes.bb_matrices(l, m)
+    nq = hx.shape[1]
+    h = np.zeros((pr.m, pr.n), np.uint8)
+    for j in range(pr.n):
+        h[pr.rowidx[pr.colptr[j]:pr.colptr[j + 1]], j] = 1
+    X, Z, Y = h[:, :nq], h[:, nq:2 * nq], h[:, 2 * nq:]
+    assert ((X ^ Z) == Y).all()
+    assert (X[:hx.shape[0]] == 0).all() and (Z[hx.shape[0]:] == 0).all()
+    np.testing.assert_array_equal(Z[:hx.shape[0]], hx)
+    np.testing.assert_array_equal(X[hx.shape[0]:], hz)
+    Lx, Lz, Ly = pr.L[:, :nq], pr.L[:, nq:2 * nq], pr.L[:, 2 * nq:]
+    assert ((Lx ^ Lz) == Ly).all() and pr.L.shape[0] == 24 == gf2.rank(pr.L)
+    np.testing.assert_allclose(pr.p, 0.02)
+    # stabilizer generators as errors: X-type (rows of H_X) in the X block,
+    # Z-type (rows of H_Z) in the Z block
+    for stab, block in ((hx, 0), (hz, 1)):
+        for r in stab[:5]:
+            e = np.zeros(pr.n, np.uint8)
+            e[block * nq:(block + 1) * nq] = r
+            assert not ((h.astype(int) @ e) % 2).any()
+            assert not ((pr.L.astype(int) @ e) % 2).any()
+    # logical operators as errors: undetected, nontrivial
+    for lg, block in ((codes.x_logicals(hx, hz), 0), (codes.x_logicals(hz, hx), 1)):
+        for r in lg:
+            e = np.zeros(pr.n, np.uint8)
+            e[block * nq:(block + 1) * nq] = r
+            assert not ((h.astype(int) @ e) % 2).any()
+            assert ((pr.L.astype(int) @ e) % 2).any()
