@@ -178,6 +178,83 @@ bsd_status bsd_code_autotune(bsd_code code, const bsd_params* prm, int64_t shots
 bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, int32_t* grid_blocks,
                          int32_t* lds_bytes);
 
+/* ------------------------------------------------------------------------
+ * Serving: requests that arrive over time are decoded continuously.
+ *
+ * A server keeps one persistent decoder per code running on the GPU, each on
+ * its own stream with its own share of the compute units.  Codes whose BP run
+ * fills a compute unit's LDS share three quarters of the units.  The other
+ * codes get a few small workgroups each.  Requests pass through a ring per
+ * code in pinned host memory.  The host writes the syndrome and publishes it,
+ * and the decoder claims it as soon as one of its workgroups is free.  This
+ * is the decoder's own work queue, so several requests of a code and the
+ * child runs of deep ones share the workgroups (continuous batching).  The
+ * decoder writes the outputs back into the ring row and raises that row's
+ * done flag.  Admission is by memory: a code's ring has a fixed number of
+ * rows, sized from a byte budget, and a request is admitted only when its
+ * row is free.
+ * Idle workgroups take turns (one at a time per decoder) reading the host's
+ * published count over the bus and mirroring it in device memory.
+ * The decoders must all run at once: each needs a hardware queue of its own
+ * (HIP's GPU_MAX_HW_QUEUES bounds them per process) and its compute units.
+ * Creation waits until every decoder reports that it runs, else fails with
+ * BSD_EDEVICE.
+ * A server holds its codes (bsd_code_destroy returns BSD_EBUSY meanwhile).
+ * Its kernels end when it is destroyed, or on their own after about 20 s
+ * without work. */
+typedef struct bsd_server_s* bsd_server;
+
+/* Create a server for ncodes (1..8) distinct codes of the current device.
+ *   params       host, [ncodes]: decoder of each code (batched mode)
+ *   grid_blocks  host, [ncodes] or NULL: workgroups per decoder (0 = automatic)
+ *   ring_bytes   pinned host memory for the request rings (0 = 64 MiB), split
+ *                evenly; each code gets a power of two in [64, 4096] rows
+ * Errors: BSD_EINVAL, BSD_ENOMEM, BSD_EDEVICE. */
+bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
+                             const int32_t* grid_blocks, int64_t ring_bytes, bsd_server* out);
+
+/* Submit one syndrome (host, uint8 [m], copied) for code `code`; `ticket`
+ * receives the request's number within that code.  BSD_EBUSY when the ring
+ * row it needs is still held by an earlier request (poll that one first). */
+bsd_status bsd_server_submit(bsd_server s, int32_t code, const uint8_t* syndrome, int64_t* ticket);
+
+/* If request `ticket` of `code` has finished, copy its outputs (host, may be
+ * NULL: corrections [n], logical_flips [k], converged [1], device_ticks: the
+ * decode time on the device in 100 MHz ticks) and release its ring row;
+ * BSD_EBUSY (no message) when it has not finished yet. */
+bsd_status bsd_server_poll(bsd_server s, int32_t code, int64_t ticket, uint8_t* corrections,
+                           uint8_t* logical_flips, uint8_t* converged, uint32_t* device_ticks);
+
+/* Stop the server's kernels and release it. */
+bsd_status bsd_server_destroy(bsd_server s);
+
+/* Latency summary of bsd_serve_poisson (microseconds, arrival to result as
+ * seen by the host; percentiles by nearest rank). */
+typedef struct {
+  int64_t requests;
+  double seconds;        /* first arrival to last result */
+  double offered_per_s;  /* requests / span of the arrival times */
+  double served_per_s;   /* requests / seconds */
+  double p50_us, p99_us, p999_us, max_us;
+  int64_t code_requests[8];
+  double code_p50_us[8], code_p99_us[8], code_p999_us[8];
+  int64_t admission_waits; /* requests that found their ring row busy and waited */
+} bsd_serve_report;
+
+/* Drive a server with `requests` Poisson arrivals at `rate` per second.
+ * Each arrival picks code i with probability mix[i] / sum(mix) (seeded, a
+ * counter-based generator) and takes the next syndrome of that code from
+ * syndromes[i] (host, uint8 [n_syndromes[i] x m_i], used in order,
+ * cyclically).  Outputs, all host and optional: corrections[i] [n_syndromes[i]
+ * x n_i], logical_flips[i], converged[i] by syndrome index; latency_us and
+ * code_of [requests]; report.  Runs in the calling thread until every request
+ * has been answered (errors: BSD_EDEVICE after a generous timeout). */
+bsd_status bsd_serve_poisson(bsd_server s, double rate, const double* mix, int64_t requests,
+                             const uint8_t* const* syndromes, const int64_t* n_syndromes,
+                             uint64_t seed, uint8_t* const* corrections,
+                             uint8_t* const* logical_flips, uint8_t* const* converged,
+                             double* latency_us, int32_t* code_of, bsd_serve_report* report);
+
 /* Thread-local message describing the last failure in this thread. */
 const char* bsd_last_error(void);
 

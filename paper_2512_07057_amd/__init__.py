@@ -42,6 +42,15 @@ class Stats(C.Structure):
                 ("deep_shots", C.c_int64), ("kernel_ms", C.c_double)]
 
 
+class ServeReport(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("seconds", C.c_double), ("offered_per_s", C.c_double),
+                ("served_per_s", C.c_double), ("p50_us", C.c_double), ("p99_us", C.c_double),
+                ("p999_us", C.c_double), ("max_us", C.c_double),
+                ("code_requests", C.c_int64 * 8), ("code_p50_us", C.c_double * 8),
+                ("code_p99_us", C.c_double * 8), ("code_p999_us", C.c_double * 8),
+                ("admission_waits", C.c_int64)]
+
+
 def exported_symbols_from_header(path: str = HEADER) -> list[str]:
     text = open(path).read()
     return sorted(set(re.findall(r"\b(bsd_[a-z_]+)\s*\(", text)))
@@ -73,6 +82,19 @@ def load():
     lib.bsd_code_autotune.restype = C.c_int
     lib.bsd_code_autotune.argtypes = [P, C.POINTER(Params), i64, P, i32p, i32p,
                                       C.POINTER(C.c_float), P]
+    lib.bsd_server_create.restype = C.c_int
+    lib.bsd_server_create.argtypes = [i32, C.POINTER(P), C.POINTER(Params), i32p, i64, C.POINTER(P)]
+    lib.bsd_server_submit.restype = C.c_int
+    lib.bsd_server_submit.argtypes = [P, i32, P, C.POINTER(i64)]
+    lib.bsd_server_poll.restype = C.c_int
+    lib.bsd_server_poll.argtypes = [P, i32, i64, P, P, P, C.POINTER(C.c_uint32)]
+    lib.bsd_server_destroy.restype = C.c_int
+    lib.bsd_server_destroy.argtypes = [P]
+    lib.bsd_serve_poisson.restype = C.c_int
+    lib.bsd_serve_poisson.argtypes = [P, C.c_double, C.POINTER(C.c_double), i64, C.POINTER(P),
+                                      C.POINTER(i64), C.c_uint64, C.POINTER(P), C.POINTER(P),
+                                      C.POINTER(P), C.POINTER(C.c_double), i32p,
+                                      C.POINTER(ServeReport)]
     lib.bsd_bp_run.restype = C.c_int
     lib.bsd_bp_run.argtypes = [P, P, i32p, i32, P, i32, C.c_float, i32, P, P, P, i32p, i32p, i32p,
                                C.POINTER(C.c_float), P]
@@ -223,3 +245,88 @@ class Code:
         _check(rc)
         return {"e": e_out, "sum_llr": sl, "ehat": eh, "iters": it.value,
                 "converged": bool(cv.value), "next_pos": npos.value, "score": sc.value}
+
+
+class Server:
+    """Persistent GPU decoders for several resident codes, fed continuously
+    (bsd_server_*).  Codes must outlive the server."""
+
+    def __init__(self, codes, params, grid_blocks=None, ring_bytes=0):
+        self._lib = load()
+        self.codes = list(codes)
+        n = len(self.codes)
+        hs = (C.c_void_p * n)(*[c._h for c in self.codes])
+        prm = (Params * n)(*params)
+        grid = (C.c_int32 * n)(*(grid_blocks or [0] * n))
+        h = C.c_void_p()
+        _check(self._lib.bsd_server_create(n, hs, prm, grid, int(ring_bytes), C.byref(h)))
+        self._h = h
+
+    def submit(self, code: int, syndrome) -> int | None:
+        """Submit a host uint8 [m] syndrome; returns its ticket, or None when
+        the code's ring is full."""
+        syn = np.ascontiguousarray(syndrome, dtype=np.uint8)
+        t = C.c_int64()
+        rc = self._lib.bsd_server_submit(self._h, int(code), syn.ctypes.data_as(C.c_void_p), C.byref(t))
+        if rc == BSD_EBUSY:
+            return None
+        _check(rc)
+        return t.value
+
+    def poll(self, code: int, ticket: int):
+        """Outputs of a finished request (dict) or None if it is still running."""
+        c = self.codes[code]
+        corr = np.empty(c.n, np.uint8)
+        flips = np.empty(max(c.k, 1), np.uint8)
+        conv = np.empty(1, np.uint8)
+        ticks = C.c_uint32()
+        rc = self._lib.bsd_server_poll(self._h, int(code), int(ticket), corr.ctypes.data_as(C.c_void_p),
+                                       flips.ctypes.data_as(C.c_void_p), conv.ctypes.data_as(C.c_void_p),
+                                       C.byref(ticks))
+        if rc == BSD_EBUSY:
+            return None
+        _check(rc)
+        return {"corrections": corr, "flips": flips[:c.k], "converged": int(conv[0]),
+                "device_ticks": ticks.value}
+
+    def serve_poisson(self, rate, mix, requests, syndromes, seed=0):
+        """Poisson arrivals over the codes (see bsd_serve_poisson); returns the
+        per-syndrome outputs of every code, per-request latencies and the report."""
+        n = len(self.codes)
+        syns = [np.ascontiguousarray(s_, dtype=np.uint8) for s_ in syndromes]
+        corr = [np.zeros((len(s_), c.n), np.uint8) for s_, c in zip(syns, self.codes)]
+        flips = [np.zeros((len(s_), max(c.k, 1)), np.uint8) for s_, c in zip(syns, self.codes)]
+        conv = [np.zeros(len(s_), np.uint8) for s_ in syns]
+        lat = np.zeros(int(requests), np.float64)
+        code_of = np.zeros(int(requests), np.int32)
+        rep = ServeReport()
+        arr = lambda xs: (C.c_void_p * n)(*[x.ctypes.data_as(C.c_void_p) for x in xs])
+        _check(self._lib.bsd_serve_poisson(
+            self._h, float(rate), (C.c_double * n)(*mix), int(requests), arr(syns),
+            (C.c_int64 * n)(*[len(s_) for s_ in syns]), int(seed), arr(corr), arr(flips), arr(conv),
+            lat.ctypes.data_as(C.POINTER(C.c_double)), code_of.ctypes.data_as(C.POINTER(C.c_int32)),
+            C.byref(rep)))
+        report = {f: getattr(rep, f) for f, _ in ServeReport._fields_ if not f.startswith("code_")}
+        report["per_code"] = [{"requests": rep.code_requests[i], "p50_us": rep.code_p50_us[i],
+                               "p99_us": rep.code_p99_us[i], "p999_us": rep.code_p999_us[i]}
+                              for i in range(n)]
+        outs = [{"corrections": corr[i], "flips": flips[i][:, :self.codes[i].k], "converged": conv[i]}
+                for i in range(n)]
+        return outs, lat, code_of, report
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.bsd_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

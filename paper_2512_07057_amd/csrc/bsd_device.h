@@ -754,16 +754,34 @@ __device__ __forceinline__ char* slot_ptr(const BatchArgs& a, int ctx, int s) {
 
 __device__ __forceinline__ uint32_t dev_clock() { return (uint32_t)wall_clock64(); }
 
+// Row of a shot's syndrome and outputs (serving: a ring slot).
+__device__ __forceinline__ long long io_row(const BatchArgs& a, long long shot) {
+  return a.stream ? (long long)((unsigned long long)shot & a.io_mask) : shot;
+}
+
+// Serving: make the shot's outputs visible to the host, then raise its flag.
+// Called by every thread after it has written its part of the outputs.
+__device__ __forceinline__ void publish_done(const BatchArgs& a, long long shot) {
+  if (!a.stream) return;
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&a.done_flag[io_row(a, shot)], (uint32_t)(shot + 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Write the shot's outputs from a slot's hard-decision bits and retire the context.
 __device__ __forceinline__ void finish_deep(const BatchArgs& a, const Lds& L, int ctx,
                                             long long shot, const uint32_t* bits, int converged,
                                             uint32_t t_start) {
   const DevGraph& g = a.g;
-  emit_from_bits(g, L, bits, a.corr + shot * g.n, a.flips + shot * g.k);
+  const long long row = io_row(a, shot);
+  emit_from_bits(g, L, bits, a.corr + row * g.n, a.flips + row * g.k);
   if (threadIdx.x == 0) {
-    a.conv[shot] = (uint8_t)converged;
-    if (a.lat) a.lat[shot] = dev_clock() - t_start;
+    a.conv[row] = (uint8_t)converged;
+    if (a.lat) a.lat[row] = dev_clock() - t_start;
   }
+  publish_done(a, shot);
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -944,7 +962,8 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   // read returns on the same counter as LDS operations.
   const uint32_t t0 = (a.lat && threadIdx.x < 64) ? dev_clock() : 0u;
   RunRegs<CPT> rg;
-  const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + shot * g.m,
+  const long long row = io_row(a, shot);
+  const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + row * g.m,
                                     a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
                                     &a.fi, pf_shot == shot, pf);
   pf_shot = -1;
@@ -954,13 +973,14 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   if ((rr.conv && !many) || a.max_rounds == 0) {
     // Read the work queue's length now: the load completes while the shot is
     // written out, and the next scheduling step skips the queue when empty.
-    emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + shot * g.n, a.flips + shot * g.k, a, R,
-                        next_shot, pf_shot, pf, work_hint);
+    emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, a, R,
+                            next_shot, pf_shot, pf, work_hint);
     if (threadIdx.x == 0) {
-      a.conv[shot] = (uint8_t)rr.conv;
-      if (a.lat) a.lat[shot] = dev_clock() - t0;
+      a.conv[row] = (uint8_t)rr.conv;
+      if (a.lat) a.lat[row] = dev_clock() - t0;
       __hip_atomic_fetch_add(&a.st->done, 1ull, __ATOMIC_RELAXED, AGENT);
     }
+    publish_done(a, shot);
     return false;
   }
   float score;
@@ -1036,7 +1056,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
     RunRegs<CPT> rg;
     const bool many = a.num_results > 1;  // converged children keep branching; no cancellation
     const RunRes rr = bp_run<CPT, PW>(g, L, R, (const float*)pslot, nullptr, np + 1,
-                                      a.syn + shot * g.m, a.round_iters, true, a.alpha,
+                                      a.syn + io_row(a, shot) * g.m, a.round_iters, true, a.alpha,
                                       many ? nullptr : &C->best_gen, c, rg, &a.st->error);
     nruns += 1;
     niters += rr.iters;
@@ -1089,11 +1109,15 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   load_res<CPT, PW>(a.g, L, R);
   unsigned long long nruns = 0, niters = 0;
   const int tid = threadIdx.x;
+  if (a.stream && blockIdx.x == 0 && tid == 0)
+    __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
   long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
   bool exhausted = false;         // thread 0 only
   int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
+  bool idling = false;            // thread 0 only, serving: in an idle stretch since idle_since
+  uint32_t idle_since = 0;
   long long pf_shot = -1;         // shot whose syndrome bits `pf` holds (uniform)
   uint32_t pf = 0;
   int32_t* misc = L.misc();
@@ -1108,6 +1132,25 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       work_hint = -1;
       if (try_work && ring_pop(&a.st->work, a.work_ring, &item)) {
         kind = 1;
+      } else if (a.stream) {
+        // Serving: take the next published shot, if any, with a spare context.
+        if (spare < 0) {
+          uint32_t cx;
+          if (ring_pop(&a.st->ctxq, a.ctx_ring, &cx)) spare = (int)cx;
+        }
+        if (spare >= 0) {
+          const unsigned long long pub = __hip_atomic_load(&a.st->pub, __ATOMIC_ACQUIRE, AGENT);
+          unsigned long long b = __hip_atomic_load(&a.st->next_shot, __ATOMIC_RELAXED, AGENT);
+          if (b < pub && __hip_atomic_compare_exchange_strong(&a.st->next_shot, &b, b + 1ull,
+                                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                              AGENT)) {
+            // The syndrome was written by the host before it published the count.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            kind = 2;
+            shot = (long long)b;
+            item = (uint32_t)spare;
+          }
+        }
       } else if (!exhausted) {
         if (spare < 0) {
           uint32_t cx;
@@ -1136,10 +1179,40 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
         }
       }
       if (kind == 0) {
-        if (__hip_atomic_load(&a.st->done, __ATOMIC_ACQUIRE, AGENT) >= (unsigned long long)a.shots)
+        if (a.stream) {
+          // One idle workgroup at a time reads the host's counters (over the
+          // bus) and mirrors them for the others.
+          if (__hip_atomic_load(&a.st->poll_token, __ATOMIC_RELAXED, AGENT) == 0u) {
+            uint32_t zero = 0u;
+            if (__hip_atomic_compare_exchange_strong(&a.st->poll_token, &zero, 1u, __ATOMIC_ACQUIRE,
+                                                     __ATOMIC_RELAXED, AGENT)) {
+              const unsigned long long ph =
+                  __hip_atomic_load(a.pub_host, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+              const uint32_t sh = __hip_atomic_load(a.stop_host, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+              if (ph > __hip_atomic_load(&a.st->pub, __ATOMIC_RELAXED, AGENT))
+                __hip_atomic_store(&a.st->pub, ph, __ATOMIC_RELEASE, AGENT);
+              if (sh) __hip_atomic_store(&a.st->stop, 1u, __ATOMIC_RELEASE, AGENT);
+              __hip_atomic_store(&a.st->poll_token, 0u, __ATOMIC_RELEASE, AGENT);
+            }
+          }
+          const uint32_t now = dev_clock();
+          if (!idling) {
+            idling = true;
+            idle_since = now;
+          }
+          if (__hip_atomic_load(&a.st->stop, __ATOMIC_ACQUIRE, AGENT) ||
+              now - idle_since > a.idle_limit)
+            kind = 3;
+          else
+            __builtin_amdgcn_s_sleep(16);
+        } else if (__hip_atomic_load(&a.st->done, __ATOMIC_ACQUIRE, AGENT) >=
+                   (unsigned long long)a.shots) {
           kind = 3;
-        else
+        } else {
           __builtin_amdgcn_s_sleep(8);
+        }
+      } else {
+        idling = false;
       }
       box[0] = kind;
       box[1] = (int)item;

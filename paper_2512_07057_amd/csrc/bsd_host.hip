@@ -11,13 +11,16 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bsd.h"
@@ -73,8 +76,6 @@ struct bsd_code_s {
   std::vector<float> lam_host;        // prior LLRs as uploaded
   std::vector<double> lam64_host;     // the same in double precision: wt(e) terms (Appendix B)
   double* d_lam64 = nullptr;
-  uint32_t* d_results = nullptr;      // num_results > 1: per-context result bit-vectors
-  size_t results_words = 0;
   uint32_t* d_resbits = nullptr;      // plain form: the chosen result's bits
   std::vector<uint32_t> cedge_host;   // LDS position | rank << 16, CSC order
   // First-iteration tables (for one alpha at a time).
@@ -83,17 +84,8 @@ struct bsd_code_s {
   bool fi_valid = false;
   uint4* d_rows = nullptr;
   uint32_t* d_negbits = nullptr;
-  // Batched workspace (grown on demand).
-  int ws_bw = 0;
-  int nctx = 0;
-  BatchState* st = nullptr;
-  BatchState* st_host = nullptr;  // pinned
-  uint32_t* work_ring = nullptr;
-  uint32_t work_cap = 0;
-  uint32_t* ctx_ring = nullptr;
-  uint32_t ctx_cap = 0;
-  Ctx* ctxs = nullptr;
-  char* slots = nullptr;
+  // Batched workspace of bsd_decode (grown on demand).
+  BatchWs ws;
   size_t slot_stride = 0;
   // Plain-form and single-run workspace.
   char* pslots = nullptr;
@@ -115,19 +107,15 @@ struct bsd_code_s {
 
 namespace {
 
-void free_workspace(bsd_code c) {
-  hipFree(c->st);
-  hipHostFree(c->st_host);
-  hipFree(c->work_ring);
-  hipFree(c->ctx_ring);
-  hipFree(c->ctxs);
-  hipFree(c->slots);
-  c->st = nullptr;
-  c->st_host = nullptr;
-  c->work_ring = c->ctx_ring = nullptr;
-  c->ctxs = nullptr;
-  c->slots = nullptr;
-  c->ws_bw = 0;
+void ws_free(BatchWs& w) {
+  hipFree(w.st);
+  hipHostFree(w.st_host);
+  hipFree(w.work_ring);
+  hipFree(w.ctx_ring);
+  hipFree(w.ctxs);
+  hipFree(w.slots);
+  hipFree(w.results);
+  w = BatchWs{};
 }
 
 void drop_graph(bsd_code c) {
@@ -138,32 +126,47 @@ void drop_graph(bsd_code c) {
   c->gkey.clear();
 }
 
-bsd_status ensure_batched(bsd_code c, int bw) {
-  if (c->ws_bw >= bw && c->st && c->nctx >= c->grid + 64) return BSD_OK;
-  drop_graph(c);
-  free_workspace(c);
-  hipFree(c->d_results);
-  c->d_results = nullptr;
-  c->results_words = 0;
-  const int nctx = c->grid + 64;
-  const int per = 3 * bw + 1;
-  c->slot_stride = slot_bytes(c->g);
-  const size_t slot_total = (size_t)nctx * per * c->slot_stride;
-  c->work_cap = pow2_at_least((uint64_t)nctx * 2 * bw + 1);
-  c->ctx_cap = pow2_at_least((uint64_t)nctx + 1);
-  if (hipMalloc((void**)&c->st, sizeof(BatchState)) != hipSuccess ||
-      hipHostMalloc((void**)&c->st_host, sizeof(BatchState), hipHostMallocDefault) != hipSuccess ||
-      hipMalloc((void**)&c->work_ring, (size_t)c->work_cap * 4) != hipSuccess ||
-      hipMalloc((void**)&c->ctx_ring, (size_t)c->ctx_cap * 4) != hipSuccess ||
-      hipMalloc((void**)&c->ctxs, (size_t)nctx * sizeof(Ctx)) != hipSuccess ||
-      hipMalloc((void**)&c->slots, slot_total) != hipSuccess) {
-    free_workspace(c);
-    (void)hipGetLastError();
-    return fail(BSD_ENOMEM, "cannot allocate the batched workspace (%zu bytes of slots)", slot_total);
+// Allocate (or grow) a batched workspace for beam width bw, nctx contexts and
+// num_results results per context.
+bsd_status ws_ensure(const DevGraph& g, BatchWs& w, int bw, int nctx, int num_results) {
+  if (!(w.bw >= bw && w.st && w.nctx >= nctx)) {
+    ws_free(w);
+    const int per = 3 * bw + 1;
+    const size_t slot_total = (size_t)nctx * per * slot_bytes(g);
+    w.work_cap = pow2_at_least((uint64_t)nctx * 2 * bw + 1);
+    w.ctx_cap = pow2_at_least((uint64_t)nctx + 1);
+    if (hipMalloc((void**)&w.st, sizeof(BatchState)) != hipSuccess ||
+        hipHostMalloc((void**)&w.st_host, sizeof(BatchState), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&w.work_ring, (size_t)w.work_cap * 4) != hipSuccess ||
+        hipMalloc((void**)&w.ctx_ring, (size_t)w.ctx_cap * 4) != hipSuccess ||
+        hipMalloc((void**)&w.ctxs, (size_t)nctx * sizeof(Ctx)) != hipSuccess ||
+        hipMalloc((void**)&w.slots, slot_total) != hipSuccess) {
+      ws_free(w);
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot allocate the batched workspace (%zu bytes of slots)", slot_total);
+    }
+    w.nctx = nctx;
+    w.bw = bw;
   }
-  c->nctx = nctx;
-  c->ws_bw = bw;
+  const size_t need = (size_t)w.nctx * num_results * g.words_n;
+  if (num_results > 1 && w.results_words < need) {
+    hipFree(w.results);
+    w.results = nullptr;
+    w.results_words = 0;
+    if (hipMalloc((void**)&w.results, need * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot allocate %zu bytes for num_results = %d", need * 4, num_results);
+    }
+    w.results_words = need;
+  }
   return BSD_OK;
+}
+
+bsd_status ensure_batched(bsd_code c, int bw, int num_results) {
+  const BatchWs before = c->ws;
+  bsd_status st = ws_ensure(c->g, c->ws, bw, c->grid + 64, num_results);
+  if (c->ws.st != before.st || c->ws.results != before.results) drop_graph(c);
+  return st;
 }
 
 bsd_status ensure_plain(bsd_code c, int bw) {
@@ -483,43 +486,15 @@ bsd_status ensure_first(bsd_code c, float alpha) {
   return BSD_OK;
 }
 
-// Result bit-vectors of every context for num_results > 1.
-bsd_status ensure_results(bsd_code c, int num_results) {
-  const size_t need = (size_t)c->nctx * num_results * c->g.words_n;
-  if (num_results <= 1 || c->results_words >= need) return BSD_OK;
-  drop_graph(c);
-  hipFree(c->d_results);
-  c->d_results = nullptr;
-  c->results_words = 0;
-  if (hipMalloc((void**)&c->d_results, need * 4) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(BSD_ENOMEM, "cannot allocate %zu bytes for num_results = %d", need * 4, num_results);
-  }
-  c->results_words = need;
-  return BSD_OK;
-}
-
-bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
-                          uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
-                          bsd_stats* stats, uint32_t* lat) {
-  bsd_status st = ensure_batched(c, p->beam_width);
-  if (st != BSD_OK) return st;
-  st = ensure_results(c, p->num_results);
-  if (st != BSD_OK) return st;
-  const bool table = !(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1;
-  if (table) {
-    st = ensure_first(c, p->alpha);
-    if (st != BSD_OK) return st;
-  }
+// Kernel arguments common to every batched launch on workspace w.
+bsd_status batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, BatchArgs* out) {
   BatchArgs a{};
   a.g = c->g;
-  if (table) a.fi = c->fi;
-  a.shots = shots;
-  a.syn = syn;
-  a.corr = corr;
-  a.flips = flips;
-  a.conv = conv;
-  a.lat = lat;
+  if (!(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1) {
+    bsd_status st = ensure_first(c, p->alpha);
+    if (st != BSD_OK) return st;
+    a.fi = c->fi;
+  }
   a.max_rounds = p->max_rounds;
   a.bw = p->beam_width;
   a.init_iters = p->initial_iters;
@@ -527,17 +502,35 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.num_results = p->num_results;
   a.alpha = p->alpha;
   a.lam64 = c->d_lam64;
-  a.results = c->d_results;
-  a.st = c->st;
-  a.work_ring = c->work_ring;
-  a.work_cap = c->work_cap;
-  a.ctx_ring = c->ctx_ring;
-  a.ctx_cap = c->ctx_cap;
-  a.ctxs = c->ctxs;
-  a.nctx = c->nctx;
-  a.slots = c->slots;
-  a.slot_stride = c->slot_stride;
-  a.slots_per_ctx = 3 * c->ws_bw + 1;
+  a.results = w.results;
+  a.st = w.st;
+  a.work_ring = w.work_ring;
+  a.work_cap = w.work_cap;
+  a.ctx_ring = w.ctx_ring;
+  a.ctx_cap = w.ctx_cap;
+  a.ctxs = w.ctxs;
+  a.nctx = w.nctx;
+  a.slots = w.slots;
+  a.slot_stride = slot_bytes(c->g);
+  a.slots_per_ctx = 3 * w.bw + 1;
+  *out = a;
+  return BSD_OK;
+}
+
+bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                          uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
+                          bsd_stats* stats, uint32_t* lat) {
+  bsd_status st = ensure_batched(c, p->beam_width, p->num_results);
+  if (st != BSD_OK) return st;
+  BatchArgs a{};
+  st = batch_args(c, c->ws, p, &a);
+  if (st != BSD_OK) return st;
+  a.shots = shots;
+  a.syn = syn;
+  a.corr = corr;
+  a.flips = flips;
+  a.conv = conv;
+  a.lat = lat;
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
     std::vector<char> key(sizeof a + 3 * sizeof(int));
@@ -569,9 +562,9 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
     HIP_OR_FAIL(hipEventRecord(c->ev1, s));
   }
-  HIP_OR_FAIL(hipMemcpyAsync(c->st_host, c->st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipMemcpyAsync(c->ws.st_host, c->ws.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
-  const BatchState& h = *c->st_host;
+  const BatchState& h = *c->ws.st_host;
   if (h.error) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
   if (h.done != (unsigned long long)shots)
     return fail(BSD_EDEVICE, "batched decoder finished %llu of %lld shots", h.done, (long long)shots);
@@ -795,10 +788,9 @@ bsd_status bsd_code_destroy(bsd_code c) {
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   hipFree(c->d_rows);
-  hipFree(c->d_results);
   hipFree(c->d_resbits);
   hipFree(c->d_negbits);
-  free_workspace(c);
+  ws_free(c->ws);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);
   hipFree(c->d_pairs);
@@ -1001,6 +993,419 @@ bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, con
   if (out_block) *out_block = c->block;
   if (out_grid) *out_grid = c->grid;
   if (out_ms) *out_ms = best_ms;
+  return BSD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: persistent decoders fed through rings in host memory
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+constexpr uint32_t kDecoderIdleTicks = 2000000000u;  // 20 s at 100 MHz
+
+struct ServeQ {
+  bsd_code code = nullptr;
+  bsd_params prm{};
+  hipStream_t stream = nullptr;
+  BatchWs ws;
+  int grid = 0;
+  uint32_t rows = 0;  // ring rows, a power of two
+  // Pinned host memory (device views in d_*): syndromes, outputs, flags.
+  uint8_t *syn = nullptr, *corr = nullptr, *flips = nullptr, *conv = nullptr;
+  uint32_t *lat = nullptr, *done = nullptr, *started = nullptr;
+  unsigned long long* pub = nullptr;
+  uint8_t *d_syn = nullptr, *d_corr = nullptr, *d_flips = nullptr, *d_conv = nullptr;
+  uint32_t *d_lat = nullptr, *d_done = nullptr, *d_started = nullptr;
+  unsigned long long* d_pub = nullptr;
+  uint64_t next = 0;                   // tickets issued
+  std::vector<int64_t> row_ticket;     // ticket holding each row, -1 if free
+};
+
+template <class T>
+hipError_t pinned(T** host, T** dev, size_t count) {
+  hipError_t e = hipHostMalloc((void**)host, count * sizeof(T), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  std::memset(*host, 0, count * sizeof(T));
+  return hipHostGetDevicePointer((void**)dev, *host, 0);
+}
+
+double now_us() {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+struct bsd_server_s {
+  int n = 0;
+  int device = 0;
+  ServeQ q[kMaxServe];
+  uint32_t* stop = nullptr;
+  uint32_t* d_stop = nullptr;
+  bool launched = false;
+};
+
+namespace {
+
+void server_free(bsd_server s) {
+  for (int i = 0; i < s->n; ++i) {
+    ServeQ& q = s->q[i];
+    ws_free(q.ws);
+    hipHostFree(q.syn);
+    hipHostFree(q.corr);
+    hipHostFree(q.flips);
+    hipHostFree(q.conv);
+    hipHostFree(q.lat);
+    hipHostFree(q.done);
+    hipHostFree(q.started);
+    hipHostFree(q.pub);
+    if (q.stream) hipStreamDestroy(q.stream);
+    if (q.code) q.code->busy--;
+  }
+  hipHostFree(s->stop);
+  delete s;
+}
+
+// Ask every kernel of the server to end and wait (bounded) until they have.
+bsd_status server_stop(bsd_server s) {
+  if (!s->launched) return BSD_OK;
+  __atomic_store_n(s->stop, 1u, __ATOMIC_RELEASE);
+  const double t0 = now_us();
+  for (;;) {
+    bool all = true;
+    for (int i = 0; i < s->n; ++i) all = all && hipStreamQuery(s->q[i].stream) != hipErrorNotReady;
+    if (all) break;
+    if (now_us() - t0 > 60e6) return fail(BSD_EDEVICE, "serving kernels did not stop within 60 s");
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  s->launched = false;
+  return BSD_OK;
+}
+
+bool server_alive(bsd_server s) {
+  if (!s->launched) return false;
+  for (int i = 0; i < s->n; ++i)
+    if (hipStreamQuery(s->q[i].stream) != hipErrorNotReady) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
+                             const int32_t* grid_blocks, int64_t ring_bytes, bsd_server* out) {
+  if (!out) return fail(BSD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ncodes < 1 || ncodes > kMaxServe || !codes || !params)
+    return fail(BSD_EINVAL, "need 1..%d codes and their params", kMaxServe);
+  if (ring_bytes < 0) return fail(BSD_EINVAL, "ring_bytes must be >= 0");
+  int dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  for (int i = 0; i < ncodes; ++i) {
+    if (!codes[i]) return fail(BSD_EINVAL, "code %d is NULL", i);
+    if (codes[i]->device != dev) return fail(BSD_EINVAL, "code %d lives on another device", i);
+    bsd_status st = check_params(codes[i], &params[i]);
+    if (st != BSD_OK) return st;
+    if (params[i].mode != BSD_MODE_BATCHED) return fail(BSD_EINVAL, "serving needs the batched mode");
+    for (int j = 0; j < i; ++j)
+      if (codes[j] == codes[i]) return fail(BSD_EINVAL, "code %d is listed twice", i);
+  }
+  int ncu = 0;
+  HIP_OR_FAIL(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  bsd_server s = new (std::nothrow) bsd_server_s;
+  if (!s) return fail(BSD_ENOMEM, "host allocation failed");
+  s->device = dev;
+  // Codes whose run fills a compute unit's LDS share 3/4 of the units; the
+  // others share four workgroups per remaining unit (a round of children of
+  // a deep shot then runs side by side).
+  int nbig = 0;
+  for (int i = 0; i < ncodes; ++i) nbig += codes[i]->lds > 64 * 1024;
+  const int nsmall = ncodes - nbig;
+  const int big_cus = nbig ? std::max(1, (3 * ncu / 4) / nbig) * nbig : 0;
+  const int small_grid = nsmall ? std::max(1, 4 * (ncu - big_cus) / nsmall) : 0;
+  const int64_t budget = ring_bytes > 0 ? ring_bytes : (int64_t)64 << 20;
+  for (int i = 0; i < ncodes; ++i) {
+    ServeQ& q = s->q[i];
+    bsd_code c = codes[i];
+    q.code = c;
+    c->busy++;
+    s->n = i + 1;
+    q.prm = params[i];
+    const bool big = c->lds > 64 * 1024;
+    q.grid = grid_blocks && grid_blocks[i] > 0 ? grid_blocks[i]
+             : big ? std::max(1, (3 * ncu / 4) / std::max(1, nbig))
+                   : std::min(c->grid, small_grid);
+    const DevGraph& g = c->g;
+    const size_t per = (size_t)g.m + g.n + std::max(g.k, 1) + 1 + 8;
+    uint64_t rows = 64;
+    while (rows * 2 <= 4096 && (int64_t)(rows * 2 * per) <= budget / ncodes) rows *= 2;
+    q.rows = (uint32_t)rows;
+    q.row_ticket.assign(rows, -1);
+    bsd_status st = ws_ensure(g, q.ws, q.prm.beam_width, q.grid + 64, q.prm.num_results);
+    hipError_t e = hipSuccess;
+    if (st == BSD_OK) {
+      if ((e = pinned(&q.syn, &q.d_syn, rows * g.m)) != hipSuccess ||
+          (e = pinned(&q.corr, &q.d_corr, rows * g.n)) != hipSuccess ||
+          (e = pinned(&q.flips, &q.d_flips, rows * std::max(g.k, 1))) != hipSuccess ||
+          (e = pinned(&q.conv, &q.d_conv, rows)) != hipSuccess ||
+          (e = pinned(&q.lat, &q.d_lat, rows)) != hipSuccess ||
+          (e = pinned(&q.done, &q.d_done, rows)) != hipSuccess ||
+          (e = pinned(&q.started, &q.d_started, 1)) != hipSuccess ||
+          (e = pinned(&q.pub, &q.d_pub, 1)) != hipSuccess ||
+          (e = hipStreamCreateWithFlags(&q.stream, hipStreamNonBlocking)) != hipSuccess)
+        st = fail(BSD_ENOMEM, "serving buffers for code %d: %s", i, hipGetErrorString(e));
+    }
+    if (st != BSD_OK) {
+      server_free(s);
+      return st;
+    }
+  }
+  hipError_t e = pinned(&s->stop, &s->d_stop, 1);
+  if (e != hipSuccess) {
+    server_free(s);
+    return fail(BSD_ENOMEM, "serving control: %s", hipGetErrorString(e));
+  }
+  // Arguments; reset every workspace before any persistent kernel starts.
+  std::vector<BatchArgs> args(ncodes);
+  for (int i = 0; i < ncodes; ++i) {
+    ServeQ& q = s->q[i];
+    bsd_status st = batch_args(q.code, q.ws, &q.prm, &args[i]);
+    hipError_t he = st == BSD_OK ? set_kernel_limits(q.code->cpt, q.code->pw, q.code->lds) : hipSuccess;
+    if (st == BSD_OK && he != hipSuccess) st = fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
+    if (st != BSD_OK) {
+      server_free(s);
+      return st;
+    }
+    BatchArgs& a = args[i];
+    a.stream = 1;
+    a.io_mask = q.rows - 1;
+    a.syn = q.d_syn;
+    a.corr = q.d_corr;
+    a.flips = q.d_flips;
+    a.conv = q.d_conv;
+    a.lat = q.d_lat;
+    a.done_flag = q.d_done;
+    a.pub_host = q.d_pub;
+    a.stop_host = s->d_stop;
+    a.started = q.d_started;
+    a.idle_limit = kDecoderIdleTicks;
+    a.shots = 0;
+    he = launch_batch_reset(a, q.stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(q.stream);
+    if (he != hipSuccess) {
+      server_free(s);
+      return fail(BSD_EDEVICE, "serving reset: %s", hipGetErrorString(he));
+    }
+  }
+  // Largest LDS first, so that the compute units they need are still free.
+  std::vector<int> order(ncodes);
+  for (int i = 0; i < ncodes; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return s->q[x].code->lds > s->q[y].code->lds; });
+  s->launched = true;
+  for (int i : order) {
+    ServeQ& q = s->q[i];
+    hipError_t he = launch_batched(args[i], q.grid, q.code->block, q.code->cpt, q.code->pw,
+                                   q.code->lds, q.stream);
+    if (he != hipSuccess) {
+      (void)server_stop(s);
+      server_free(s);
+      return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
+    }
+  }
+  // Every kernel must be running at once (none may wait behind another on a
+  // shared hardware queue or for compute units): wait for each to report.
+  const double t0 = now_us();
+  for (;;) {
+    bool all = true;
+    for (int i = 0; i < ncodes; ++i) all = all && __atomic_load_n(s->q[i].started, __ATOMIC_ACQUIRE) != 0;
+    if (all) break;
+    if (now_us() - t0 > 5e6) {
+      std::string which;
+      for (int i = 0; i < ncodes; ++i)
+        if (!__atomic_load_n(s->q[i].started, __ATOMIC_ACQUIRE)) which += " decoder" + std::to_string(i);
+      const bsd_status st = server_stop(s);
+      if (st == BSD_OK) server_free(s);
+      return fail(BSD_EDEVICE, "serving kernels did not all start within 5 s (not running:%s); "
+                  "more hardware queues (GPU_MAX_HW_QUEUES) or fewer workgroups may be needed",
+                  which.c_str());
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+  *out = s;
+  return BSD_OK;
+}
+
+bsd_status bsd_server_submit(bsd_server s, int32_t code, const uint8_t* syndrome, int64_t* ticket) {
+  if (!s || code < 0 || code >= s->n || !syndrome) return fail(BSD_EINVAL, "bad server, code or syndrome");
+  ServeQ& q = s->q[code];
+  const DevGraph& g = q.code->g;
+  const uint64_t t = q.next;
+  const uint32_t row = (uint32_t)(t & (q.rows - 1));
+  if (q.row_ticket[row] >= 0) return fail(BSD_EBUSY, "ring of code %d is full", code);
+  if (!server_alive(s)) return fail(BSD_EDEVICE, "serving kernels have stopped");
+  for (int i = 0; i < g.m; ++i)
+    if (syndrome[i] > 1) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  std::memcpy(q.syn + (size_t)row * g.m, syndrome, g.m);
+  q.row_ticket[row] = (int64_t)t;
+  q.next = t + 1;
+  __atomic_store_n(q.pub, (unsigned long long)(t + 1), __ATOMIC_RELEASE);
+  if (ticket) *ticket = (int64_t)t;
+  return BSD_OK;
+}
+
+bsd_status bsd_server_poll(bsd_server s, int32_t code, int64_t ticket, uint8_t* corrections,
+                           uint8_t* logical_flips, uint8_t* converged, uint32_t* device_ticks) {
+  if (!s || code < 0 || code >= s->n || ticket < 0) return fail(BSD_EINVAL, "bad server, code or ticket");
+  ServeQ& q = s->q[code];
+  const DevGraph& g = q.code->g;
+  const uint32_t row = (uint32_t)((uint64_t)ticket & (q.rows - 1));
+  if (q.row_ticket[row] != ticket) return fail(BSD_EINVAL, "ticket %lld is not in flight", (long long)ticket);
+  if (__atomic_load_n(&q.done[row], __ATOMIC_ACQUIRE) != (uint32_t)(ticket + 1)) {
+    if (!server_alive(s)) return fail(BSD_EDEVICE, "serving kernels have stopped");
+    return BSD_EBUSY;  // not finished yet (no error message)
+  }
+  if (corrections) std::memcpy(corrections, q.corr + (size_t)row * g.n, g.n);
+  if (logical_flips) std::memcpy(logical_flips, q.flips + (size_t)row * std::max(g.k, 1), g.k);
+  if (converged) *converged = q.conv[row];
+  if (device_ticks) *device_ticks = q.lat[row];
+  q.row_ticket[row] = -1;
+  return BSD_OK;
+}
+
+bsd_status bsd_server_destroy(bsd_server s) {
+  if (!s) return BSD_OK;
+  bsd_status st = server_stop(s);
+  if (st != BSD_OK) return st;  // kernels still running: keep their memory
+  server_free(s);
+  return BSD_OK;
+}
+
+bsd_status bsd_serve_poisson(bsd_server s, double rate, const double* mix, int64_t requests,
+                             const uint8_t* const* syndromes, const int64_t* n_syndromes,
+                             uint64_t seed, uint8_t* const* corrections,
+                             uint8_t* const* logical_flips, uint8_t* const* converged,
+                             double* latency_us, int32_t* code_of, bsd_serve_report* report) {
+  if (!s || !(rate > 0) || !mix || requests < 0 || !syndromes || !n_syndromes)
+    return fail(BSD_EINVAL, "bad serving arguments");
+  const int n = s->n;
+  double cum[kMaxServe], tot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!(mix[i] >= 0) || n_syndromes[i] < 1 || !syndromes[i]) return fail(BSD_EINVAL, "bad mix or inputs for code %d", i);
+    tot += mix[i];
+    cum[i] = tot;
+  }
+  if (!(tot > 0)) return fail(BSD_EINVAL, "mix sums to zero");
+  // Arrival times (exponential gaps) and codes from a counter-based generator.
+  struct Req {
+    double t;
+    int code;
+    int64_t idx, ticket;
+  };
+  std::vector<Req> req((size_t)requests);
+  std::vector<int64_t> used(n, 0);
+  uint64_t x = seed;
+  auto next_u = [&]() {
+    x += 0x9e3779b97f4a7c15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  };
+  double t = 0;
+  for (int64_t k = 0; k < requests; ++k) {
+    t += -std::log(next_u()) / rate * 1e6;
+    const double u = next_u() * tot;
+    int c = 0;
+    while (c < n - 1 && u >= cum[c]) ++c;
+    req[k] = {t, c, used[c]++ % n_syndromes[c], -1};
+  }
+  std::vector<double> lat((size_t)requests, 0.0);
+  std::vector<std::deque<int64_t>> waiting(n), inflight(n);
+  int64_t next_arrival = 0, completed = 0, waits = 0;
+  std::vector<uint8_t> waited((size_t)requests, 0);
+  const double span = requests ? req[requests - 1].t : 0.0;
+  const double start = now_us();
+  const double deadline = start + std::max(30e6, 20.0 * span);
+  double last_done = start;
+  while (completed < requests) {
+    const double now = now_us();
+    if (now > deadline) return fail(BSD_EDEVICE, "serving loop timed out with %lld of %lld done",
+                                    (long long)completed, (long long)requests);
+    while (next_arrival < requests && req[next_arrival].t <= now - start)
+      waiting[req[next_arrival].code].push_back(next_arrival), ++next_arrival;
+    for (int c = 0; c < n; ++c) {
+      while (!waiting[c].empty()) {
+        Req& r = req[waiting[c].front()];
+        const int64_t k = waiting[c].front();
+        const bsd_status st = bsd_server_submit(s, c, syndromes[c] + r.idx * s->q[c].code->g.m, &r.ticket);
+        if (st == BSD_EBUSY) {
+          if (!waited[k]) ++waits;
+          waited[k] = 1;
+          break;
+        }
+        if (st != BSD_OK) return st;
+        waiting[c].pop_front();
+        inflight[c].push_back(k);
+      }
+    }
+    for (int c = 0; c < n; ++c) {
+      const DevGraph& g = s->q[c].code->g;
+      for (auto it = inflight[c].begin(); it != inflight[c].end();) {
+        Req& r = req[*it];
+        uint8_t* co = corrections && corrections[c] ? corrections[c] + r.idx * g.n : nullptr;
+        uint8_t* fl = logical_flips && logical_flips[c] ? logical_flips[c] + r.idx * g.k : nullptr;
+        uint8_t* cv = converged && converged[c] ? converged[c] + r.idx : nullptr;
+        const bsd_status st = bsd_server_poll(s, c, r.ticket, co, fl, cv, nullptr);
+        if (st == BSD_EBUSY) {
+          ++it;
+          continue;
+        }
+        if (st != BSD_OK) return st;
+        const double tn = now_us();
+        lat[*it] = tn - start - r.t;
+        last_done = tn;
+        ++completed;
+        it = inflight[c].erase(it);
+      }
+    }
+  }
+  if (latency_us) std::memcpy(latency_us, lat.data(), lat.size() * sizeof(double));
+  if (code_of)
+    for (int64_t k = 0; k < requests; ++k) code_of[k] = req[k].code;
+  if (report) {
+    bsd_serve_report r{};
+    r.requests = requests;
+    r.seconds = (last_done - start) * 1e-6;
+    r.offered_per_s = span > 0 ? requests / (span * 1e-6) : 0.0;
+    r.served_per_s = r.seconds > 0 ? requests / r.seconds : 0.0;
+    r.admission_waits = waits;
+    auto pct = [](std::vector<double> v, double q) {  // nearest rank
+      if (v.empty()) return 0.0;
+      std::sort(v.begin(), v.end());
+      const double rank = std::max(0.0, std::ceil(q * (double)v.size()) - 1.0);
+      return v[std::min(v.size() - 1, (size_t)rank)];
+    };
+    r.p50_us = pct(lat, 0.50);
+    r.p99_us = pct(lat, 0.99);
+    r.p999_us = pct(lat, 0.999);
+    r.max_us = pct(lat, 1.0);
+    for (int c = 0; c < n; ++c) {
+      std::vector<double> v;
+      for (int64_t k = 0; k < requests; ++k)
+        if (req[k].code == c) v.push_back(lat[k]);
+      r.code_requests[c] = (int64_t)v.size();
+      r.code_p50_us[c] = pct(v, 0.50);
+      r.code_p99_us[c] = pct(v, 0.99);
+      r.code_p999_us[c] = pct(v, 0.999);
+    }
+    *report = r;
+  }
   return BSD_OK;
 }
 

@@ -95,6 +95,11 @@ struct BatchState {
   uint32_t pad;
   Ring work;
   Ring ctxq;
+  // Serving: mirrors of the host's published count and stop flag, refreshed
+  // by whichever idle workgroup holds the poll token.
+  unsigned long long pub;  // shots published
+  uint32_t stop;           // nonzero: end the kernel
+  uint32_t poll_token;     // 1 while a workgroup is reading the host counters
 };
 
 // The check phase of iteration 1 in a run from the priors with no masked
@@ -111,11 +116,36 @@ struct FirstIter {
   int32_t enabled;
 };
 
+// Device workspace of one batched decoder instance: queue state, rings,
+// per-shot contexts and their path slots.
+struct BatchWs {
+  int bw = 0, nctx = 0;
+  BatchState* st = nullptr;
+  BatchState* st_host = nullptr;  // pinned copy for read-back
+  uint32_t* work_ring = nullptr;
+  uint32_t work_cap = 0;
+  uint32_t* ctx_ring = nullptr;
+  uint32_t ctx_cap = 0;
+  Ctx* ctxs = nullptr;
+  char* slots = nullptr;
+  uint32_t* results = nullptr;  // num_results > 1
+  size_t results_words = 0;
+};
+
 struct BatchArgs {
   DevGraph g;
   FirstIter fi;
   const double* lam64;    // [n] wt(e) contributions log((1-p_j)/p_j) in double precision
   uint32_t* results;      // num_results > 1: [nctx][num_results][words_n] e-hat bits
+  // Serving (stream != 0): shots arrive over time through a ring of
+  // io_mask + 1 rows in host memory; `shots` is unused.
+  int32_t stream;
+  unsigned long long io_mask;  // row of a shot's input and outputs = shot & io_mask
+  const unsigned long long* pub_host;  // host memory: shots published
+  const uint32_t* stop_host;           // host memory: nonzero ends the kernel
+  uint32_t* done_flag;         // per row: low 32 bits of shot + 1 once its outputs are written
+  uint32_t* started;           // host memory: set to 1 when the kernel's first workgroup runs
+  uint32_t idle_limit;         // also end after this many 100 MHz ticks with nothing to do
   long long shots;
   const uint8_t* syn;
   uint8_t* corr;
@@ -178,6 +208,8 @@ hipError_t launch_single(const SingleArgs& a, int block, int cpt, int pw, size_t
 hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, int pw, size_t lds,
                           hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+
+constexpr int kMaxServe = 8;  // codes one server can hold
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 hipError_t set_kernel_limits(int cpt, int pw, size_t lds);
 hipError_t batched_occupancy(int cpt, int pw, int block, size_t lds, int* blocks_per_cu);

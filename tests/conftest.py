@@ -4,6 +4,11 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# The serving tests keep three persistent decoders on streams of their own:
+# ask HIP for enough hardware queues that none of them waits behind another
+# kernel.  Read when HIP initialises, which no test module does at import.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
