@@ -42,7 +42,8 @@ class Pair(C.Structure):
 class Params(C.Structure):
     _fields_ = [("max_rounds", C.c_int32), ("beam_width", C.c_int32),
                 ("initial_iters", C.c_int32), ("iters_per_round", C.c_int32),
-                ("num_results", C.c_int32), ("alpha", C.c_double), ("llr_max", C.c_double)]
+                ("num_results", C.c_int32), ("alpha", C.c_double), ("llr_max", C.c_double),
+                ("alpha_sched", C.POINTER(C.c_double)), ("n_alpha", C.c_int32)]
 
 
 class ShotDiag(C.Structure):
@@ -184,16 +185,22 @@ class OracleProblem:
         return npos.value, sc.value
 
     def decode(self, syndromes, max_rounds, beam_width, initial_iters, iters_per_round,
-               num_results=1, alpha=0.625, dtype=np.float64, threads=0, llr_max=LLR_MAX):
-        """Beam-search decoding (Algorithm 3) of a batch of syndromes."""
+               num_results=1, alpha=0.625, dtype=np.float64, threads=0, llr_max=LLR_MAX,
+               alpha_sched=None):
+        """Beam-search decoding (Algorithm 3) of a batch of syndromes;
+        `alpha_sched` (optional) scales iteration t of every BP run by
+        alpha_sched[min(t, len) - 1]."""
         syn = np.ascontiguousarray(syndromes, dtype=np.uint8).reshape(-1, self.m)
         shots = syn.shape[0]
         corr = np.zeros((shots, self.n), np.uint8)
         flips = np.zeros((shots, self.k), np.uint8)
         conv = np.zeros(shots, np.uint8)
         diag = np.zeros(shots, DIAG_DTYPE)
+        sched = None if alpha_sched is None else np.ascontiguousarray(alpha_sched, dtype=np.float64)
         prm = Params(int(max_rounds), int(beam_width), int(initial_iters), int(iters_per_round),
-                     int(num_results), float(alpha), float(llr_max))
+                     int(num_results), float(alpha), float(llr_max),
+                     _ptr(sched, C.c_double) if sched is not None else None,
+                     0 if sched is None else len(sched))
         suf = "f64" if np.dtype(dtype) == np.float64 else "f32"
         rc = getattr(self._lib, f"oracle_decode_{suf}")(
             self._h, C.byref(prm), shots, _ptr(syn, C.c_uint8), _ptr(corr, C.c_uint8),
@@ -203,7 +210,7 @@ class OracleProblem:
             raise ValueError("oracle decode rejected its arguments")
         return {"corrections": corr, "flips": flips, "converged": conv, "diag": diag}
 
-    def decode_params(self, syndromes, params, dtype=np.float64, threads=0):
+    def decode_params(self, syndromes, params, dtype=np.float64, threads=0, alpha_sched=None):
         return self.decode(syndromes, params.max_rounds, params.beam_width, params.initial_iters,
                            params.iters_per_round, params.num_results, params.alpha,
-                           dtype=dtype, threads=threads)
+                           dtype=dtype, threads=threads, alpha_sched=alpha_sched)

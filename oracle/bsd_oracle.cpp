@@ -80,9 +80,18 @@ inline T saturate(T x, T lim, int64_t& clamps) {
 }
 
 // Algorithm 2 (masked_BP), built on the min-sum updates of Appendix A.
+// Scaling of eq. (1) at iteration t (1-based): the schedule's entry, the last
+// one past its end, or the single alpha.
+template <class T>
+T alpha_at(T alpha, const std::vector<T>& sched, int t) {
+  if (sched.empty()) return alpha;
+  return sched[std::min<size_t>((size_t)t, sched.size()) - 1];
+}
+
 template <class T>
 void masked_bp(const Problem& P, const T* e_start, const std::vector<oracle_pair>& pairs,
-               const uint8_t* s, int max_iters, T alpha, T llr_max, bool stop, RunOut<T>& out) {
+               const uint8_t* s, int max_iters, T alpha, T llr_max, bool stop, RunOut<T>& out,
+               const std::vector<T>& sched = {}) {
   const int m = P.m, n = P.n;
   const int nnz = P.colptr[n];
   const std::vector<T>& lam = lambda_of<T>(P);
@@ -107,6 +116,7 @@ void masked_bp(const Problem& P, const T* e_start, const std::vector<oracle_pair
   out.iters = 0;
 
   for (int t = 1; t <= max_iters; ++t) {
+    const T at = alpha_at<T>(alpha, sched, t);
     // Eq. (1): detector-to-error messages from E(t-1), unmasked neighbours only.
     for (int i = 0; i < m; ++i) {
       const std::vector<int>& nb = P.row_edges[i];
@@ -120,7 +130,7 @@ void masked_bp(const Problem& P, const T* e_start, const std::vector<oracle_pair
           T ab = std::fabs(E[b]);
           if (ab < mag) mag = ab;
         }
-        T d = saturate<T>(alpha * mag, llr_max, out.clamps);
+        T d = saturate<T>(at * mag, llr_max, out.clamps);
         D[a] = negative ? -d : d;
       }
     }
@@ -223,6 +233,8 @@ void decode_one(const Problem& P, const oracle_params& prm, const uint8_t* s, ui
                 uint8_t* flips, uint8_t* conv, oracle_shot_diag& dg) {
   const int n = P.n;
   const T alpha = (T)prm.alpha, lmax = (T)prm.llr_max;
+  std::vector<T> sched;
+  for (int i = 0; i < prm.n_alpha; ++i) sched.push_back((T)prm.alpha_sched[i]);
   const int want = prm.num_results;
   dg.min_abs_post = std::numeric_limits<double>::infinity();
   dg.min_nextpos_gap = std::numeric_limits<double>::infinity();
@@ -273,7 +285,7 @@ void decode_one(const Problem& P, const oracle_params& prm, const uint8_t* s, ui
   // Initial standard BP run from the priors.
   RunOut<T> r0;
   std::vector<oracle_pair> none;
-  masked_bp<T>(P, nullptr, none, s, prm.initial_iters, alpha, lmax, true, r0);
+  masked_bp<T>(P, nullptr, none, s, prm.initial_iters, alpha, lmax, true, r0, sched);
   account(r0);
   if (r0.converged) {
     add_result(r0.ehat, 0, 0);
@@ -312,7 +324,8 @@ void decode_one(const Problem& P, const oracle_params& prm, const uint8_t* s, ui
         ch.pairs.push_back(oracle_pair{par.next_pos, v});
         ch.gen = (int)(2 * kk + v);
         RunOut<T> rr;
-        masked_bp<T>(P, par.e.data(), ch.pairs, s, prm.iters_per_round, alpha, lmax, true, rr);
+        masked_bp<T>(P, par.e.data(), ch.pairs, s, prm.iters_per_round, alpha, lmax, true, rr,
+                     sched);
         account(rr);
         if (rr.converged) {
           add_result(rr.ehat, r, ch.gen);
@@ -411,6 +424,7 @@ int decode_impl(oracle_problem h, const oracle_params* prm, int64_t shots, const
   if (!P || !prm || shots < 0 || (shots && (!syn || !corr || !flips || !conv))) return -1;
   if (prm->beam_width < 1 || prm->max_rounds < 0 || prm->initial_iters < 0 ||
       prm->iters_per_round < 0 || prm->num_results < 1 || !(prm->alpha > 0) ||
+      prm->n_alpha < 0 || (prm->n_alpha > 0 && !prm->alpha_sched) ||
       !(prm->llr_max > 0))
     return -1;
   int nt = threads > 0 ? threads : (int)std::thread::hardware_concurrency();

@@ -34,6 +34,11 @@ typedef struct {
   int32_t max_rounds, beam_width, initial_iters, iters_per_round, num_results;
   double alpha;   /* min-sum scaling applied to eq. (1); 1.0 is eq. (1) as printed */
   double llr_max; /* saturation of every D and E message (and of an empty min) */
+  /* Optional per-iteration scaling: iteration t of every BP run (initial and
+   * masked) scales eq. (1) by alpha_sched[min(t, n_alpha) - 1] instead of
+   * alpha.  NULL / 0: alpha throughout. */
+  const double* alpha_sched;
+  int32_t n_alpha;
 } oracle_params;
 
 typedef struct {

@@ -106,3 +106,43 @@ def test_gradients_equal_central_differences(w0, T):
         am[t] -= h
         fd = (f(lam, ap) - f(lam, am)) / (2 * h)
         assert abs(fd - ga[t]) <= 1e-6 * (1 + abs(fd)), (t, fd, ga[t])
+
+
+def test_constant_schedule_equals_single_alpha(oracle_mod, w0):
+    pr, g, d = w0
+    op = oracle_mod.OracleProblem.from_problem(pr)
+    syn = d["syndromes"][:64]
+    a = op.decode(syn, 6, 8, 20, 8, alpha=0.625, dtype=np.float32)
+    b = op.decode(syn, 6, 8, 20, 8, alpha=0.9, dtype=np.float32, alpha_sched=[0.625] * 5)
+    for k in ("corrections", "flips", "converged"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_schedule_initial_run_is_unrolled_minsum_stopped_at_a_solution(oracle_mod, w0):
+    """max_rounds = 0 with a schedule: the decision is that of the first
+    iteration whose hard decision satisfies He = s (eq. (4) on the unrolled
+    posteriors), else of the last iteration."""
+    pr, g, d = w0
+    op = oracle_mod.OracleProblem.from_problem(pr)
+    rng = np.random.default_rng(11)
+    alpha = rng.uniform(0.4, 1.0, 6)
+    T = 9  # beyond the schedule: the last entry repeats
+    sched_full = np.concatenate([alpha, np.full(T - len(alpha), alpha[-1])])
+    syn = d["syndromes"][:12]
+    lam = torch.tensor(np.log((1 - pr.p) / pr.p))
+    H = np.zeros((pr.m, pr.n), np.int64)
+    for j in range(pr.n):
+        H[pr.rowidx[pr.colptr[j]:pr.colptr[j + 1]], j] = 1
+    got = op.decode(syn, 0, 8, T, 8, dtype=np.float64, alpha_sched=alpha)
+    for b in range(len(syn)):
+        want = None
+        for t in range(1, T + 1):
+            post = U.unrolled_minsum(g, lam, torch.tensor(sched_full[:t]), syn[b:b + 1])[0].numpy()
+            eh = (post <= 0).astype(np.int64)
+            if ((H @ eh) % 2 == syn[b]).all():
+                want = (eh, 1)
+                break
+        if want is None:
+            want = (eh, 0)
+        np.testing.assert_array_equal(got["corrections"][b], want[0])
+        assert got["converged"][b] == want[1]
