@@ -80,7 +80,11 @@ typedef enum {
    * the factor (-1)^{s_i}, and the table holds the s = 0 values formed with
    * the kernels' own single-precision operations.  Results are identical
    * either way; this flag exists to check that. */
-  BSD_FLAG_DENSE_FIRST = 2
+  BSD_FLAG_DENSE_FIRST = 2,
+  /* Scale eq. (1) at iteration t of every BP run (initial and masked) by the
+   * code's schedule entry min(t, n) (bsd_code_set_alpha_schedule) instead of
+   * alpha: the per-iteration factors the unrolled decoder learns. */
+  BSD_FLAG_ALPHA_SCHEDULE = 4
 } bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */
@@ -173,6 +177,11 @@ bsd_status bsd_code_autotune(bsd_code code, const bsd_params* prm, int64_t shots
                              const uint8_t* syndromes, int32_t* block_threads,
                              int32_t* grid_blocks, float* best_ms, void* stream);
 
+/* Set (n > 0, host floats, each positive and finite; copied) or clear
+ * (n = 0) the per-iteration scaling schedule that BSD_FLAG_ALPHA_SCHEDULE
+ * selects.  BSD_EBUSY while a decode on the code is running. */
+bsd_status bsd_code_set_alpha_schedule(bsd_code code, int32_t n, const float* alphas);
+
 /* Geometry of a code handle: nnz of H and the threads per workgroup and
  * workgroups the batched kernel will use.  Any pointer may be NULL. */
 bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, int32_t* grid_blocks,
@@ -254,6 +263,43 @@ bsd_status bsd_serve_poisson(bsd_server s, double rate, const double* mix, int64
                              uint64_t seed, uint8_t* const* corrections,
                              uint8_t* const* logical_flips, uint8_t* const* converged,
                              double* latency_us, int32_t* code_of, bsd_serve_report* report);
+
+/* ------------------------------------------------------------------------
+ * Differentiable unrolled min-sum (training the decoder's factors).
+ *
+ * Forward: T flooding iterations of min-sum (Appendix A, eqs. (1)-(3)) from
+ * E(0) = Lambda, with the messages of eq. (1) scaled by alpha_t at
+ * iteration t, no early stop; output post(T), the final posterior LLRs (the
+ * final marginal is P(e_j = 1) = 1 / (1 + exp(post_j))).  Messages are
+ * saturated to +-1e30 as in the decoder.  The adjoint gives dL/dLambda and
+ * dL/dalpha from dL/dpost(T), recomputing every K iterations from
+ * checkpoints E(0), E(K), E(2K), ... written by the forward pass.  It is
+ * exact wherever no check has a tie between its two smallest |E| and no
+ * message is 0 (there the map is not differentiable), and treats the
+ * saturation as inactive.  One wavefront per shot with the shot's messages
+ * in LDS: (K + 3) * nnz + n elements must fit in 160 KB.
+ *
+ * Arrays are device memory of element size elem_bytes (4: float, 8: double)
+ * and belong to the caller:
+ *   syndromes    uint8 [shots x m] (0/1)
+ *   lambda       [n] prior LLRs;   alpha [T] scalings
+ *   post         [shots x n] output of the forward pass
+ *   checkpoints  [shots x ceil(T/K) x nnz] (bsd_unroll_sizes), written by the
+ *                forward pass and read by the backward pass (E in CSC order)
+ *   grad_post    [shots x n] dL/dpost(T)
+ *   grad_lambda  [n], grad_alpha [T] outputs, summed over shots in shot order
+ *   workspace    [shots x (n + T)] scratch of the backward pass
+ * Both calls are asynchronous on `stream`.  Errors: BSD_EINVAL, BSD_ENOMEM,
+ * BSD_EDEVICE. */
+bsd_status bsd_unroll_sizes(bsd_code code, int32_t T, int32_t K, int64_t shots,
+                            int64_t* checkpoint_elems, int64_t* workspace_elems);
+bsd_status bsd_unroll_forward(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K, int64_t shots,
+                              const uint8_t* syndromes, const void* lambda, const void* alpha,
+                              void* post, void* checkpoints, void* stream);
+bsd_status bsd_unroll_backward(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K, int64_t shots,
+                               const uint8_t* syndromes, const void* lambda, const void* alpha,
+                               const void* checkpoints, const void* grad_post, void* grad_lambda,
+                               void* grad_alpha, void* workspace, void* stream);
 
 /* Thread-local message describing the last failure in this thread. */
 const char* bsd_last_error(void);

@@ -21,6 +21,7 @@ BSD_OK, BSD_EINVAL, BSD_ENOMEM, BSD_EDEVICE, BSD_EBUSY = 0, -1, -2, -3, -4
 MODE_BATCHED, MODE_PLAIN = 0, 1
 FLAG_GRAPH = 1
 FLAG_DENSE_FIRST = 2
+FLAG_ALPHA_SCHEDULE = 4
 _lib = None
 
 
@@ -73,6 +74,8 @@ def load():
                                     C.POINTER(P)]
     lib.bsd_code_destroy.restype = C.c_int
     lib.bsd_code_destroy.argtypes = [P]
+    lib.bsd_code_set_alpha_schedule.restype = C.c_int
+    lib.bsd_code_set_alpha_schedule.argtypes = [P, i32, C.POINTER(C.c_float)]
     lib.bsd_code_info.restype = C.c_int
     lib.bsd_code_info.argtypes = [P, C.POINTER(i64), i32p, i32p, i32p]
     lib.bsd_decode.restype = C.c_int
@@ -95,6 +98,12 @@ def load():
                                       C.POINTER(i64), C.c_uint64, C.POINTER(P), C.POINTER(P),
                                       C.POINTER(P), C.POINTER(C.c_double), i32p,
                                       C.POINTER(ServeReport)]
+    lib.bsd_unroll_sizes.restype = C.c_int
+    lib.bsd_unroll_sizes.argtypes = [P, i32, i32, i64, C.POINTER(i64), C.POINTER(i64)]
+    lib.bsd_unroll_forward.restype = C.c_int
+    lib.bsd_unroll_forward.argtypes = [P, i32, i32, i32, i64, P, P, P, P, P, P]
+    lib.bsd_unroll_backward.restype = C.c_int
+    lib.bsd_unroll_backward.argtypes = [P, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P]
     lib.bsd_bp_run.restype = C.c_int
     lib.bsd_bp_run.argtypes = [P, P, i32p, i32, P, i32, C.c_float, i32, P, P, P, i32p, i32p, i32p,
                                C.POINTER(C.c_float), P]
@@ -176,6 +185,12 @@ class Code:
             self.close()
         except Exception:
             pass
+
+    def set_alpha_schedule(self, alphas):
+        """Per-iteration scalings used with FLAG_ALPHA_SCHEDULE (None clears)."""
+        a = np.ascontiguousarray([] if alphas is None else alphas, dtype=np.float32)
+        _check(self._lib.bsd_code_set_alpha_schedule(self._h, len(a),
+                                                     a.ctypes.data_as(C.POINTER(C.c_float))))
 
     def decode(self, syndromes, params: Params, stream=None, latency=False, out=None):
         """Decode a [shots, m] uint8 CUDA tensor; returns a dict of tensors and stats."""
@@ -330,3 +345,62 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _unrolled_function():
+    import torch
+
+    class UnrolledMinSum(torch.autograd.Function):
+        """post(T) of unrolled min-sum (bsd_unroll_forward) with the
+        hand-written adjoint (bsd_unroll_backward) as its backward."""
+
+        @staticmethod
+        def forward(ctx, lam, alpha, syndromes, code, K):
+            lib = load()
+            if lam.dtype not in (torch.float32, torch.float64) or alpha.dtype != lam.dtype:
+                raise ValueError("lam and alpha must share a float32 or float64 dtype")
+            if not (lam.is_cuda and alpha.is_cuda and syndromes.is_cuda):
+                raise ValueError("lam, alpha and syndromes must be CUDA tensors")
+            lam, alpha = lam.contiguous(), alpha.contiguous()
+            syn = syndromes.contiguous()
+            if syn.dtype != torch.uint8 or syn.dim() != 2 or syn.shape[1] != code.m:
+                raise ValueError(f"syndromes must be uint8 [shots, {code.m}]")
+            shots, T = syn.shape[0], alpha.numel()
+            ck_n, ws_n = C.c_int64(), C.c_int64()
+            _check(lib.bsd_unroll_sizes(code._h, T, int(K), shots, C.byref(ck_n), C.byref(ws_n)))
+            post = torch.empty((shots, code.n), dtype=lam.dtype, device=lam.device)
+            ck = torch.empty(max(ck_n.value, 1), dtype=lam.dtype, device=lam.device)
+            _check(lib.bsd_unroll_forward(code._h, lam.element_size(), T, int(K), shots, _ptr(syn),
+                                          _ptr(lam), _ptr(alpha), _ptr(post), _ptr(ck), _stream(None)))
+            ctx.save_for_backward(lam, alpha, syn, ck)
+            ctx.code, ctx.K, ctx.ws_n = code, int(K), ws_n.value
+            return post
+
+        @staticmethod
+        def backward(ctx, grad_post):
+            lib = load()
+            lam, alpha, syn, ck = ctx.saved_tensors
+            code = ctx.code
+            g = grad_post.contiguous().to(lam.dtype)
+            gl = torch.empty_like(lam)
+            ga = torch.empty_like(alpha)
+            ws = torch.empty(max(ctx.ws_n, 1), dtype=lam.dtype, device=lam.device)
+            _check(lib.bsd_unroll_backward(code._h, lam.element_size(), alpha.numel(), ctx.K,
+                                           syn.shape[0], _ptr(syn), _ptr(lam), _ptr(alpha), _ptr(ck),
+                                           _ptr(g), _ptr(gl), _ptr(ga), _ptr(ws), _stream(None)))
+            return gl, ga, None, None, None
+
+    return UnrolledMinSum
+
+
+def unrolled_minsum(code: "Code", lam, alpha, syndromes, K: int = 5):
+    """Differentiable post(T) [shots, n] of T = len(alpha) flooding min-sum
+    iterations with per-iteration scaling alpha and priors lam (CUDA tensors,
+    float32 or float64); checkpoints every K iterations."""
+    global _UNROLLED
+    if _UNROLLED is None:
+        _UNROLLED = _unrolled_function()
+    return _UNROLLED.apply(lam, alpha, syndromes, code, K)
+
+
+_UNROLLED = None

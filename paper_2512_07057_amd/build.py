@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsd.so")
 SOURCES = ["bsd_kernels_common.hip", "bsd_kernels_pw1.hip", "bsd_kernels_pw2.hip",
-           "bsd_kernels_pw3.hip", "bsd_kernels_pw4.hip", "bsd_host.hip"]
+           "bsd_kernels_pw3.hip", "bsd_kernels_pw4.hip", "bsd_unroll.hip", "bsd_host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

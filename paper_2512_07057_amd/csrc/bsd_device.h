@@ -369,7 +369,8 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
                                          const uint8_t* syn, int T, bool stop, float alpha,
                                          const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
                                          uint32_t* err, const FirstIter* fi = nullptr,
-                                         bool have_pf = false, uint32_t pf = 0u) {
+                                         bool have_pf = false, uint32_t pf = 0u,
+                                         const float* asched = nullptr, int nsched = 0) {
   const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
   const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
@@ -490,12 +491,13 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
     uint32_t* resid = L.resid(t & 1);
     if (!(table && t == 1)) {
       for (int w = tid; w < g.words_m; w += B) resid[w] = L.sprime()[w];
+      const float at = asched ? asched[min(t, nsched) - 1] : alpha;
       if (npairs) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) check_rows<true>(g, L, R.row[q], q * B + tid, alpha);
+        for (int q = 0; q < 2; ++q) check_rows<true>(g, L, R.row[q], q * B + tid, at);
       } else {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) check_rows<false>(g, L, R.row[q], q * B + tid, alpha);
+        for (int q = 0; q < 2; ++q) check_rows<false>(g, L, R.row[q], q * B + tid, at);
       }
       lds_barrier();
     }
@@ -965,7 +967,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   const long long row = io_row(a, shot);
   const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + row * g.m,
                                     a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
-                                    &a.fi, pf_shot == shot, pf);
+                                    &a.fi, pf_shot == shot, pf, a.alpha_sched, a.n_sched);
   pf_shot = -1;
   nruns += 1;
   niters += rr.iters;
@@ -1057,7 +1059,8 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
     const bool many = a.num_results > 1;  // converged children keep branching; no cancellation
     const RunRes rr = bp_run<CPT, PW>(g, L, R, (const float*)pslot, nullptr, np + 1,
                                       a.syn + io_row(a, shot) * g.m, a.round_iters, true, a.alpha,
-                                      many ? nullptr : &C->best_gen, c, rg, &a.st->error);
+                                      many ? nullptr : &C->best_gen, c, rg, &a.st->error, nullptr,
+                                      false, 0u, a.alpha_sched, a.n_sched);
     nruns += 1;
     niters += rr.iters;
     uint32_t* mbitsv = (uint32_t*)(mslot + slot_ehat_off(g));
@@ -1257,7 +1260,8 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_single(SingleArgs a) {
   __syncthreads();
   RunRegs<CPT> rg;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, a.parent, a.parent_csc, a.npairs, a.syn, a.max_iters,
-                                    a.stop != 0, a.alpha, nullptr, 0, rg, a.error);
+                                    a.stop != 0, a.alpha, nullptr, 0, rg, a.error, nullptr, false, 0u,
+                                    a.alpha_sched, a.n_sched);
   float score = 0.f;
   int next_pos = -1;
   if (a.want_score) score_next<CPT>(g, L, rg, rr.iters, &score, &next_pos);

@@ -77,6 +77,9 @@ struct bsd_code_s {
   std::vector<double> lam64_host;     // the same in double precision: wt(e) terms (Appendix B)
   double* d_lam64 = nullptr;
   uint32_t* d_resbits = nullptr;      // plain form: the chosen result's bits
+  int32_t *u_colptr = nullptr, *u_rowptr = nullptr, *u_rowedge = nullptr;  // unrolled decoder
+  std::vector<float> asched;          // per-iteration scaling (BSD_FLAG_ALPHA_SCHEDULE)
+  float* d_asched = nullptr;
   std::vector<uint32_t> cedge_host;   // LDS position | rank << 16, CSC order
   // First-iteration tables (for one alpha at a time).
   FirstIter fi{};
@@ -208,7 +211,8 @@ bsd_status check_params(const bsd_code c, const bsd_params* p) {
     return fail(BSD_EINVAL, "alpha must be positive and finite");
   if (p->mode != BSD_MODE_BATCHED && p->mode != BSD_MODE_PLAIN)
     return fail(BSD_EINVAL, "unknown mode %d", p->mode);
-  (void)c;
+  if ((p->flags & BSD_FLAG_ALPHA_SCHEDULE) && c->asched.empty())
+    return fail(BSD_EINVAL, "BSD_FLAG_ALPHA_SCHEDULE without a schedule (bsd_code_set_alpha_schedule)");
   return BSD_OK;
 }
 
@@ -220,9 +224,13 @@ struct RunOut {
 // One BP run of the plain form: pairs up, launch, result down (synchronous).
 bsd_status plain_run(bsd_code c, hipStream_t s, const float* parent, const std::vector<int32_t>& pairs,
                      const uint8_t* syn, int T, float alpha, float* out_msg, uint32_t* out_bits,
-                     RunOut* r, bool keep_msg = false) {
+                     RunOut* r, bool keep_msg = false, bool sched = false) {
   SingleArgs a{};
   a.g = c->g;
+  if (sched) {
+    a.alpha_sched = c->d_asched;
+    a.n_sched = (int32_t)c->asched.size();
+  }
   a.parent = parent;
   a.npairs = (int)pairs.size();
   if (!pairs.empty()) {
@@ -269,6 +277,7 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
   const int bw = p->beam_width;
   const int want = p->num_results;
   const bool many = want > 1;  // converged runs keep their messages and keep branching
+  const bool sched = (p->flags & BSD_FLAG_ALPHA_SCHEDULE) != 0;
   auto slot = [&](int i) { return c->pslots + (size_t)i * c->slot_stride; };
   auto msg_of = [&](int i) { return (float*)slot(i); };
   auto bits_of = [&](int i) { return (uint32_t*)(slot(i) + slot_ehat_off(g)); };
@@ -304,7 +313,7 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
     res_wt.clear();
     RunOut r0;
     st = plain_run(c, s, nullptr, {}, sq, p->initial_iters, p->alpha, msg_of(0), bits_of(keeper), &r0,
-                   many);
+                   many, sched);
     if (st != BSD_OK) return st;
     ++runs;
     iters += r0.iters;
@@ -337,7 +346,7 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
             free_slots.pop_back();
             RunOut rr;
             st = plain_run(c, s, msg_of(set[k].slot), ch.pairs, sq, p->iters_per_round, p->alpha,
-                           msg_of(ch.slot), bits_of(ch.slot), &rr, many);
+                           msg_of(ch.slot), bits_of(ch.slot), &rr, many, sched);
             if (st != BSD_OK) return st;
             ++runs;
             iters += rr.iters;
@@ -490,10 +499,15 @@ bsd_status ensure_first(bsd_code c, float alpha) {
 bsd_status batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, BatchArgs* out) {
   BatchArgs a{};
   a.g = c->g;
+  const bool sched = (p->flags & BSD_FLAG_ALPHA_SCHEDULE) != 0;
   if (!(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1) {
-    bsd_status st = ensure_first(c, p->alpha);
+    bsd_status st = ensure_first(c, sched ? c->asched[0] : p->alpha);  // iteration 1's scaling
     if (st != BSD_OK) return st;
     a.fi = c->fi;
+  }
+  if (sched) {
+    a.alpha_sched = c->d_asched;
+    a.n_sched = (int32_t)c->asched.size();
   }
   a.max_rounds = p->max_rounds;
   a.bw = p->beam_width;
@@ -789,6 +803,10 @@ bsd_status bsd_code_destroy(bsd_code c) {
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   hipFree(c->d_rows);
   hipFree(c->d_resbits);
+  hipFree(c->d_asched);
+  hipFree(c->u_colptr);
+  hipFree(c->u_rowptr);
+  hipFree(c->u_rowedge);
   hipFree(c->d_negbits);
   ws_free(c->ws);
   for (void* p : c->owned) hipFree(p);
@@ -800,6 +818,26 @@ bsd_status bsd_code_destroy(bsd_code c) {
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   delete c;
+  return BSD_OK;
+}
+
+bsd_status bsd_code_set_alpha_schedule(bsd_code c, int32_t n, const float* alphas) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  if (n < 0 || n > 4096 || (n > 0 && !alphas)) return fail(BSD_EINVAL, "need 0 <= n <= 4096 scalings");
+  for (int i = 0; i < n; ++i)
+    if (!(alphas[i] > 0.f) || !std::isfinite(alphas[i]))
+      return fail(BSD_EINVAL, "scaling %d must be positive and finite", i);
+  std::lock_guard<std::mutex> lock(c->mu);
+  if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
+  drop_graph(c);
+  hipFree(c->d_asched);
+  c->d_asched = nullptr;
+  c->asched.assign(alphas, alphas + n);
+  if (n > 0 && dev_upload(&c->d_asched, c->asched) != hipSuccess) {
+    (void)hipGetLastError();
+    c->asched.clear();
+    return fail(BSD_ENOMEM, "cannot upload the schedule");
+  }
   return BSD_OK;
 }
 
@@ -1406,6 +1444,120 @@ bsd_status bsd_serve_poisson(bsd_server s, double rate, const double* mix, int64
     }
     *report = r;
   }
+  return BSD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Differentiable unrolled min-sum
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+bsd_status unroll_prepare(bsd_code c, int32_t elem, int32_t T, int32_t K, int64_t shots,
+                          UnrollArgs* a) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  if (elem != 4 && elem != 8) return fail(BSD_EINVAL, "element size must be 4 (float) or 8 (double)");
+  if (T < 0 || T > 4096 || K < 1 || shots < 0 || shots > (int64_t)1 << 31)
+    return fail(BSD_EINVAL, "need 0 <= T <= 4096, K >= 1, 0 <= shots < 2^31");
+  const DevGraph& g = c->g;
+  if (!c->u_colptr) {
+    std::vector<int32_t> rp(g.m + 1, 0), re(g.nnz);
+    for (int e = 0; e < g.nnz; ++e) rp[c->rowidx[e] + 1]++;
+    for (int i = 0; i < g.m; ++i) rp[i + 1] += rp[i];
+    std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+    for (int j = 0; j < g.n; ++j)  // ascending column within each row
+      for (int e = c->colptr[j]; e < c->colptr[j + 1]; ++e) re[fill[c->rowidx[e]]++] = e;
+    if (dev_upload(&c->u_colptr, c->colptr) != hipSuccess || dev_upload(&c->u_rowptr, rp) != hipSuccess ||
+        dev_upload(&c->u_rowedge, re) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot upload the unrolled decoder's tables");
+    }
+  }
+  UnrollArgs u{};
+  u.m = g.m;
+  u.n = g.n;
+  u.nnz = g.nnz;
+  u.T = T;
+  u.K = K;
+  u.nseg = (T + K - 1) / K;
+  u.colptr = c->u_colptr;
+  u.rowptr = c->u_rowptr;
+  u.rowedge = c->u_rowedge;
+  u.shots = shots;
+  u.llr_max = kLlrMax;
+  if (unroll_bwd_lds(u, elem) > (size_t)kLdsBytes)
+    return fail(BSD_EINVAL, "graph too large for the unrolled decoder: %zu bytes of LDS with K = %d",
+                unroll_bwd_lds(u, elem), K);
+  *a = u;
+  return BSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bsd_status bsd_unroll_sizes(bsd_code code, int32_t T, int32_t K, int64_t shots,
+                            int64_t* checkpoint_elems, int64_t* workspace_elems) {
+  UnrollArgs a{};
+  bsd_status st = unroll_prepare(code, 8, T, K, shots, &a);
+  if (st != BSD_OK) return st;
+  if (checkpoint_elems) *checkpoint_elems = shots * (int64_t)a.nseg * a.nnz;
+  if (workspace_elems) *workspace_elems = shots * (int64_t)(a.n + a.T);
+  return BSD_OK;
+}
+
+bsd_status bsd_unroll_forward(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K, int64_t shots,
+                              const uint8_t* syndromes, const void* lambda, const void* alpha,
+                              void* post, void* checkpoints, void* stream) {
+  UnrollArgs a{};
+  bsd_status st = unroll_prepare(code, elem_bytes, T, K, shots, &a);
+  if (st != BSD_OK) return st;
+  if (shots == 0) return BSD_OK;
+  if (!syndromes || !lambda || (T > 0 && !alpha) || !post || (T > 0 && !checkpoints))
+    return fail(BSD_EINVAL, "NULL buffer");
+  a.syn = syndromes;
+  a.lam = lambda;
+  a.alpha = alpha;
+  a.post = post;
+  a.ckpt = checkpoints;
+  int dev_prev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev_prev));
+  HIP_OR_FAIL(hipSetDevice(code->device));
+  const hipError_t e = launch_unroll_forward(a, elem_bytes, (hipStream_t)stream);
+  (void)hipSetDevice(dev_prev);
+  if (e != hipSuccess) return fail(BSD_EDEVICE, "unrolled forward: %s", hipGetErrorString(e));
+  return BSD_OK;
+}
+
+bsd_status bsd_unroll_backward(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K, int64_t shots,
+                               const uint8_t* syndromes, const void* lambda, const void* alpha,
+                               const void* checkpoints, const void* grad_post, void* grad_lambda,
+                               void* grad_alpha, void* workspace, void* stream) {
+  UnrollArgs a{};
+  bsd_status st = unroll_prepare(code, elem_bytes, T, K, shots, &a);
+  if (st != BSD_OK) return st;
+  if (!grad_lambda || (T > 0 && !grad_alpha)) return fail(BSD_EINVAL, "NULL gradient buffer");
+  if (shots > 0 && (!syndromes || !lambda || (T > 0 && !alpha) || (T > 0 && !checkpoints) ||
+                    !grad_post || !workspace))
+    return fail(BSD_EINVAL, "NULL buffer");
+  a.syn = syndromes;
+  a.lam = lambda;
+  a.alpha = alpha;
+  a.ckpt = const_cast<void*>(checkpoints);  // read only by the backward kernels
+  a.gpost = grad_post;
+  a.gl_part = workspace;
+  a.ga_part = static_cast<char*>(workspace) + (size_t)shots * a.n * elem_bytes;
+  a.grad_lam = grad_lambda;
+  a.grad_alpha = grad_alpha;
+  int dev_prev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev_prev));
+  HIP_OR_FAIL(hipSetDevice(code->device));
+  const hipError_t e = launch_unroll_backward(a, elem_bytes, (hipStream_t)stream);
+  (void)hipSetDevice(dev_prev);
+  if (e != hipSuccess) return fail(BSD_EDEVICE, "unrolled backward: %s", hipGetErrorString(e));
   return BSD_OK;
 }
 

@@ -154,6 +154,8 @@ struct BatchArgs {
   uint32_t* lat;
   int32_t max_rounds, bw, init_iters, round_iters, num_results;
   float alpha;
+  const float* alpha_sched;  // or NULL: iteration t scales eq. (1) by alpha_sched[min(t, n_sched) - 1]
+  int32_t n_sched;
   BatchState* st;
   uint32_t* work_ring;
   uint32_t work_cap;      // power of two
@@ -177,6 +179,8 @@ struct SingleArgs {
   int32_t max_iters;
   int32_t stop;
   float alpha;
+  const float* alpha_sched;  // as in BatchArgs
+  int32_t n_sched;
   int32_t want_score;
   float* out_msg;           // LDS order, written when not converged or keep_msg (or NULL)
   int32_t keep_msg;
@@ -210,6 +214,31 @@ hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, int 
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 
 constexpr int kMaxServe = 8;  // codes one server can hold
+
+// Differentiable unrolled min-sum (bsd_unroll.hip).  Graph in CSC order
+// (edge = CSC position) with each row's edges in ascending column order.
+constexpr int kUnrollBlock = 64;  // one wave per shot
+struct UnrollArgs {
+  int32_t m, n, nnz, T, K, nseg;  // nseg = ceil(T / K) checkpoints per shot
+  const int32_t* colptr;          // [n + 1]
+  const int32_t* rowptr;          // [m + 1]
+  const int32_t* rowedge;         // [nnz]
+  long long shots;
+  const uint8_t* syn;             // [shots][m]
+  const void* lam;                // [n]
+  const void* alpha;              // [T]
+  void* post;                     // forward output [shots][n]
+  void* ckpt;                     // [shots][nseg][nnz]: E(0), E(K), E(2K), ...
+  const void* gpost;              // backward input [shots][n]
+  void* gl_part;                  // [shots][n] per-shot dL/dLambda
+  void* ga_part;                  // [shots][T] per-shot dL/dalpha
+  void* grad_lam;                 // [n]
+  void* grad_alpha;               // [T]
+  double llr_max;
+};
+hipError_t launch_unroll_forward(const UnrollArgs& a, int elem, hipStream_t s);
+hipError_t launch_unroll_backward(const UnrollArgs& a, int elem, hipStream_t s);
+size_t unroll_bwd_lds(const UnrollArgs& a, int elem);
 hipError_t launch_emit(const EmitArgs& a, hipStream_t s);
 hipError_t set_kernel_limits(int cpt, int pw, size_t lds);
 hipError_t batched_occupancy(int cpt, int pw, int block, size_t lds, int* blocks_per_cu);

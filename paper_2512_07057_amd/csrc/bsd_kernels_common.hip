@@ -31,6 +31,40 @@ __global__ void k_batch_reset(BatchArgs a) {
   }
 }
 
+
+// Final output of one shot from a hard-decision bit-vector (plain form).
+__global__ void k_emit(EmitArgs a) {
+  __shared__ uint32_t flw[2 * kMaxWaves];
+  const DevGraph& g = a.g;
+  unsigned long long f = 0;
+  for (int j = threadIdx.x; j < g.n; j += blockDim.x) {
+    uint32_t b = (a.ehat_bits[j >> 5] >> (j & 31)) & 1u;
+    for (int q = 0; q < a.nfill; ++q)
+      if ((a.fill_pairs[q] >> 1) == j) b = (uint32_t)(a.fill_pairs[q] & 1);
+    a.corr[j] = (uint8_t)b;
+    if (b) f ^= g.lmask[j];
+  }
+  uint32_t lo = (uint32_t)f, hi = (uint32_t)(f >> 32);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo ^= __shfl_xor(lo, o, 64);
+    hi ^= __shfl_xor(hi, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    flw[2 * wave] = lo;
+    flw[2 * wave + 1] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < nw; ++w)
+      t ^= (unsigned long long)flw[2 * w] | ((unsigned long long)flw[2 * w + 1] << 32);
+    for (int r = 0; r < g.k; ++r) a.flips[r] = (uint8_t)((t >> r) & 1ull);
+    a.conv[0] = (uint8_t)a.converged;
+  }
+}
+
 }  // namespace
 
 size_t lds_bytes_for(const DevGraph& g) { return (dev::lds_need(g) + 15) & ~(size_t)15; }
