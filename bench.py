@@ -69,9 +69,19 @@ def cpu_baseline(pr, params, syn_all, target_s=10.0):
     t0 = time.perf_counter()
     op.decode_params(syn_all[:n], params, dtype=np.float64, threads=cores)
     dt = time.perf_counter() - t0
+    # single-thread time per shot (the kind of figure the paper reports for its CPU decoder)
+    nl = min(1000, len(syn_all))
+    per = np.empty(nl)
+    for i in range(nl):
+        t1 = time.perf_counter()
+        op.decode_params(syn_all[i:i + 1], params, dtype=np.float64, threads=1)
+        per[i] = (time.perf_counter() - t1) * 1e6
     return {"value": n / dt, "unit": "shots/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} of the benchmark's syndromes, double-precision oracle, "
-                      f"one shot per thread over {cores} host threads, {dt:.1f} s wall"}
+                      f"one shot per thread over {cores} host threads, {dt:.1f} s wall",
+            "single_thread_latency_us": {"p50": float(np.percentile(per, 50)),
+                                         "p99": float(np.percentile(per, 99)),
+                                         "p999": float(np.percentile(per, 99.9)), "shots": nl}}
 
 
 def serving(bsd, torch, w2_code, w2_syn, w2_corr, seconds=2.0, rate=20_000.0):
@@ -190,6 +200,13 @@ def main():
     conv = out["converged"].cpu().numpy().astype(bool)
     fails = (~conv) | (out["flips"].cpu().numpy() != data["true_flips"]).any(1)
 
+    # The same decode from host buffers (syndromes in and results out over
+    # the bus, staged by the library): the bus-inclusive rate.
+    code.decode_host(syn_h[:1000], prm)
+    th = time.perf_counter()
+    code.decode_host(syn_h, prm)
+    host_rate = shots / (time.perf_counter() - th)
+
     # Plain form: one kernel launch per BP run, beam bookkeeping on the host.
     nplain = min(args.plain_shots, shots)
     prm_plain = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
@@ -200,6 +217,10 @@ def main():
     rp = code.decode(syn[:nplain].contiguous(), prm_plain)
     torch.cuda.synchronize()
     plain_rate = nplain / (time.perf_counter() - tp)
+    # per-shot host latency of the plain form (a separate call: it synchronises every shot)
+    nlat = min(nplain, 2000)
+    rl = code.decode(syn[:nlat].contiguous(), prm_plain, latency=True)
+    plat = rl["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0
     same = bool((rp["corrections"] == out["corrections"][:nplain]).all().item())
 
     # Roofline of the batched kernel: algorithmic bytes of the two-phase
@@ -230,8 +251,14 @@ def main():
                        "max": float(lat_us.max()),
                        "what": "per shot, device clock from the start of its initial BP run "
                                "to the write of its result, inside the batched kernel"},
-        "plain": {"shots_per_s": plain_rate, "shots": nplain, "identical_to_batched": same},
+        "plain": {"shots_per_s": plain_rate, "shots": nplain, "identical_to_batched": same,
+                  "latency_us": {"p50": float(np.percentile(plat, 50)),
+                                 "p99": float(np.percentile(plat, 99)),
+                                 "p999": float(np.percentile(plat, 99.9)),
+                                 "shots": nlat, "what": "host time per shot (its launches and "
+                                                        "transfers), first shots of the batch"}},
         "batched_over_plain": value / plain_rate,
+        "host_buffers_shots_per_s": host_rate,
         "kernel_ms": kms,
         "edge_updates_per_s": float(np.mean(iters)) * pr.nnz / (kms * 1e-3),
         "bp_iterations_per_step": float(np.mean(iters)),

@@ -123,13 +123,16 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
 bsd_status bsd_code_destroy(bsd_code code);
 
 /* Decode `shots` syndromes with the beam search of Algorithm 3.
- *   syndromes      device, uint8 [shots x m], values 0/1 (s = H e)
- *   corrections    device, uint8 [shots x n]: the returned e-hat (0/1)
- *   logical_flips  device, uint8 [shots x k]: A e-hat mod 2 (compare with A e)
- *   converged      device, uint8 [shots]: 1 iff H e-hat = s was reached
+ *   syndromes      uint8 [shots x m], values 0/1 (s = H e)
+ *   corrections    uint8 [shots x n]: the returned e-hat (0/1)
+ *   logical_flips  uint8 [shots x k]: A e-hat mod 2 (compare with A e)
+ *   converged      uint8 [shots]: 1 iff H e-hat = s was reached
  *   stream         hipStream_t to run on (NULL: the default stream)
- * Buffers are owned by the caller and must not overlap.  The call returns
- * after the work on `stream` has completed (it reads back a status word).
+ * Buffers may be device memory (decoded in place) or host memory (told apart
+ * with hipPointerGetAttributes; then staged through device buffers the code
+ * handle keeps, bus transfers included).  They are owned by the caller and
+ * must not overlap.  The call returns after the work on `stream` has
+ * completed (it reads back a status word).
  * Errors: BSD_EINVAL for bad parameters or syndrome bytes outside {0,1};
  * BSD_ENOMEM when the workspace cannot be allocated; BSD_EDEVICE. */
 bsd_status bsd_decode(bsd_code code, const bsd_params* prm, int64_t shots,
@@ -137,9 +140,11 @@ bsd_status bsd_decode(bsd_code code, const bsd_params* prm, int64_t shots,
                       uint8_t* converged, void* stream);
 
 /* As bsd_decode, also filling `stats` (host, may be NULL) and, when
- * `latency_ticks` (device, uint32 [shots], may be NULL) is given, the
- * per-shot decode time in ticks of the 100 MHz device clock (from the start
- * of the shot's initial BP run to the write of its result). */
+ * `latency_ticks` (uint32 [shots], may be NULL) is given, the
+ * per-shot decode time in 10 ns ticks: batched mode, the 100 MHz device
+ * clock from the start of the shot's initial BP run to the write of its
+ * result; plain mode, the host's time for the shot (all its launches and
+ * transfers). */
 bsd_status bsd_decode_ex(bsd_code code, const bsd_params* prm, int64_t shots,
                          const uint8_t* syndromes, uint8_t* corrections, uint8_t* logical_flips,
                          uint8_t* converged, void* stream, bsd_stats* stats,

@@ -223,6 +223,23 @@ class Code:
             res["latency_ticks"] = lat
         return res
 
+    def decode_host(self, syndromes, params: Params) -> dict:
+        """Decode a host uint8 [shots, m] array; the library stages it
+        through device memory (synchronous).  Returns numpy arrays and stats."""
+        syn = np.ascontiguousarray(syndromes, dtype=np.uint8)
+        if syn.ndim != 2 or syn.shape[1] != self.m:
+            raise ValueError(f"syndromes must have shape [shots, {self.m}]")
+        shots = syn.shape[0]
+        corr = np.empty((shots, self.n), np.uint8)
+        flips = np.empty((shots, max(self.k, 1)), np.uint8)
+        conv = np.empty(shots, np.uint8)
+        st = Stats()
+        vp = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(self._lib.bsd_decode_ex(self._h, C.byref(params), shots, vp(syn), vp(corr), vp(flips),
+                                       vp(conv), None, C.byref(st), None))
+        return {"corrections": corr, "flips": flips[:, :self.k], "converged": conv,
+                "stats": {f: getattr(st, f) for f, _ in Stats._fields_}}
+
     def autotune(self, syndromes, params: Params, stream=None) -> dict:
         """Time the admissible launch geometries on `syndromes` and keep the fastest."""
         import torch

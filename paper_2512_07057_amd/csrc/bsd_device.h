@@ -682,8 +682,15 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, 
                                                long long& pf_shot, uint32_t& pf, int& work_hint) {
   const int B = blockDim.x;
   unsigned long long f = 0;
-  // All loads before the stores: a wait for a load also waits for the
-  // stores issued before it.
+  // All loads before the stores: a wait for a load also waits for every
+  // memory operation issued before it.  The logical masks (needed here) go
+  // first; the next step's loads follow and stay in flight past the wait.
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = c * B + threadIdx.x;
+    if (j < g.n && ((bits >> c) & 1u)) f ^= g.lmask[j];
+  }
+  asm volatile("" ::: "memory");  // keep the order of issue
   if (threadIdx.x == 0) work_hint = __hip_atomic_load(&a.st->work.count, __ATOMIC_RELAXED, AGENT);
   if (next_shot >= 0) {
     const uint8_t* ns = a.syn + next_shot * g.m;
@@ -694,12 +701,7 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, 
     pf = v;
     pf_shot = next_shot;
   }
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int j = c * B + threadIdx.x;
-    if (j < g.n && ((bits >> c) & 1u)) f ^= g.lmask[j];
-  }
-  asm volatile("" ::: "memory");  // keep the order of issue
+  asm volatile("" ::: "memory");
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int j = c * B + threadIdx.x;

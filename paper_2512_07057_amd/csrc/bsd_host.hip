@@ -77,6 +77,8 @@ struct bsd_code_s {
   std::vector<double> lam64_host;     // the same in double precision: wt(e) terms (Appendix B)
   double* d_lam64 = nullptr;
   uint32_t* d_resbits = nullptr;      // plain form: the chosen result's bits
+  uint8_t* d_stage = nullptr;         // staging of host buffers passed to bsd_decode
+  size_t stage_bytes = 0;
   int32_t *u_colptr = nullptr, *u_rowptr = nullptr, *u_rowedge = nullptr;  // unrolled decoder
   std::vector<float> asched;          // per-iteration scaling (BSD_FLAG_ALPHA_SCHEDULE)
   float* d_asched = nullptr;
@@ -269,7 +271,7 @@ struct HostPath {
 
 bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
                         uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
-                        bsd_stats* stats) {
+                        bsd_stats* stats, uint32_t* lat) {
   const DevGraph& g = c->g;
   bsd_status st = ensure_plain(c, p->beam_width);
   if (st != BSD_OK) return st;
@@ -301,8 +303,11 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
     *full = (int)res.size() >= want;
     return BSD_OK;
   };
+  // Per-shot host time (10 ns units, the unit of the batched form's device clock).
+  std::vector<uint32_t> lat_h(lat ? (size_t)shots : 0);
   HIP_OR_FAIL(hipEventRecord(c->ev0, s));
   for (int64_t q = 0; q < shots; ++q) {
+    const auto t_shot = std::chrono::steady_clock::now();
     const uint8_t* sq = syn + q * g.m;
     EmitArgs e{};
     e.g = g;
@@ -412,8 +417,14 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
       e.converged = emit_conv;
     }
     HIP_OR_FAIL(launch_emit(e, s));
-    if (emit_lightest) HIP_OR_FAIL(hipStreamSynchronize(s));  // res[best] is pageable host memory
+    if (emit_lightest || lat) HIP_OR_FAIL(hipStreamSynchronize(s));  // res[best] is pageable
+    if (lat)
+      lat_h[q] = (uint32_t)std::min<double>(
+          4e9, std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t_shot)
+                       .count() / 10.0);
   }
+  if (lat && shots > 0)
+    HIP_OR_FAIL(hipMemcpyAsync(lat, lat_h.data(), lat_h.size() * 4, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(hipEventRecord(c->ev1, s));
   uint32_t err = 0;
   HIP_OR_FAIL(hipMemcpyAsync(c->h_pinned + kMaxRounds + 4, c->d_error, 4, hipMemcpyDeviceToHost, s));
@@ -801,6 +812,7 @@ bsd_status bsd_code_destroy(bsd_code c) {
   if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  hipFree(c->d_stage);
   hipFree(c->d_rows);
   hipFree(c->d_resbits);
   hipFree(c->d_asched);
@@ -850,6 +862,64 @@ bsd_status bsd_code_info(bsd_code c, int64_t* nnz, int32_t* block, int32_t* grid
   return BSD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// True for memory the device can address directly (device memory, or host
+// memory allocated or registered with HIP).
+bool is_device_ptr(const void* ptr) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+         at.devicePointer != nullptr;
+}
+
+// Host buffers: copy the syndromes in and the outputs back through device
+// buffers of the code handle (grown on demand); synchronous.
+bsd_status decode_staged(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
+                         uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
+                         bsd_stats* stats, uint32_t* lat) {
+  const DevGraph& g = c->g;
+  const size_t need = (size_t)shots * (g.m + g.n + std::max(g.k, 1) + 1 + 4) + 64;
+  if (c->stage_bytes < need) {
+    hipFree(c->d_stage);
+    c->d_stage = nullptr;
+    c->stage_bytes = 0;
+    if (hipMalloc((void**)&c->d_stage, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BSD_ENOMEM, "cannot allocate %zu bytes to stage host buffers", need);
+    }
+    c->stage_bytes = need;
+    drop_graph(c);
+  }
+  uint8_t* ds = c->d_stage;
+  uint8_t* dc = ds + (size_t)shots * g.m;
+  uint8_t* df = dc + (size_t)shots * g.n;
+  uint8_t* dv = df + (size_t)shots * std::max(g.k, 1);
+  uint32_t* dl = reinterpret_cast<uint32_t*>(((uintptr_t)(dv + shots) + 15) & ~(uintptr_t)15);
+  const bool dev_syn = is_device_ptr(syn);
+  HIP_OR_FAIL(hipMemcpyAsync(ds, syn, (size_t)shots * g.m,
+                             dev_syn ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  bsd_status st = p->mode == BSD_MODE_PLAIN
+                      ? decode_plain(c, p, shots, ds, dc, df, dv, s, stats, lat ? dl : nullptr)
+                      : decode_batched(c, p, shots, ds, dc, df, dv, s, stats, lat ? dl : nullptr);
+  if (st != BSD_OK) return st;
+  HIP_OR_FAIL(hipMemcpyAsync(corr, dc, (size_t)shots * g.n, hipMemcpyDefault, s));
+  if (g.k > 0) HIP_OR_FAIL(hipMemcpyAsync(flips, df, (size_t)shots * g.k, hipMemcpyDefault, s));
+  HIP_OR_FAIL(hipMemcpyAsync(conv, dv, (size_t)shots, hipMemcpyDefault, s));
+  if (lat) HIP_OR_FAIL(hipMemcpyAsync(lat, dl, (size_t)shots * 4, hipMemcpyDefault, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  return BSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 bsd_status bsd_decode_ex(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
                          uint8_t* corr, uint8_t* flips, uint8_t* conv, void* stream,
                          bsd_stats* stats, uint32_t* lat) {
@@ -868,8 +938,14 @@ bsd_status bsd_decode_ex(bsd_code c, const bsd_params* p, int64_t shots, const u
   (void)hipGetDevice(&dev_prev);
   (void)hipSetDevice(c->device);
   hipStream_t s = (hipStream_t)stream;
-  st = p->mode == BSD_MODE_PLAIN ? decode_plain(c, p, shots, syn, corr, flips, conv, s, stats)
-                                 : decode_batched(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+  const bool staged = !is_device_ptr(syn) || !is_device_ptr(corr) || !is_device_ptr(conv) ||
+                      (c->g.k > 0 && !is_device_ptr(flips)) || (lat && !is_device_ptr(lat));
+  if (staged) {
+    st = decode_staged(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+  } else {
+    st = p->mode == BSD_MODE_PLAIN ? decode_plain(c, p, shots, syn, corr, flips, conv, s, stats, lat)
+                                   : decode_batched(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+  }
   (void)hipSetDevice(dev_prev);
   c->busy--;
   return st;

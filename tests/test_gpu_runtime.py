@@ -87,3 +87,18 @@ def test_first_iteration_table_equals_dense(bsd, wl, hot, shots):
         np.testing.assert_array_equal(a[k].cpu().numpy(), b[k].cpu().numpy())
     assert a["stats"]["deep_shots"] == b["stats"]["deep_shots"]
     gc.log(wl, hot, "dense ms", a["stats"]["kernel_ms"], "table ms", b["stats"]["kernel_ms"])
+
+
+def test_host_buffers_equal_device_buffers(bsd):
+    """bsd_decode with host memory (staged by the library) gives the outputs
+    of the same call on device memory, batched and plain."""
+    W = workloads.WORKLOADS["W1"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    syn = gc.samples("W1", 700, seed=31)["syndromes"]
+    for mode in (bsd.MODE_BATCHED, bsd.MODE_PLAIN):
+        prm = gc.params_for(bsd, W.params, mode)
+        n = 700 if mode == bsd.MODE_BATCHED else 60
+        dev = _np(code.decode(torch.from_numpy(syn[:n]).cuda(), prm))
+        host = code.decode_host(syn[:n], prm)
+        for k in dev:
+            np.testing.assert_array_equal(host[k], dev[k])
