@@ -109,6 +109,15 @@ __device__ __forceinline__ void opaque_res(Res<CPT, PW>& R) {
   asm volatile("" : "+v"(R.row[0]), "+v"(R.row[1]));
 }
 
+// threadIdx.x as a value the compiler cannot treat as loop-invariant:
+// addresses derived from it are recomputed inside the persistent loop rather
+// than kept live (and spilled) across it.
+__device__ __forceinline__ int fresh_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <int CPT>
 struct RunRegs {
   float sumllr[CPT];
@@ -317,7 +326,7 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const R
 __device__ __forceinline__ void flip_resid(const DevGraph& g, uint32_t* resid, uint32_t ebits) {
   for (uint32_t mk = ebits; mk; mk &= mk - 1u) {
     const int c = __builtin_ctz(mk);
-    const uint4 rq = g.crank[c * (int)blockDim.x + (int)threadIdx.x];
+    const uint4 rq = g.crank[c * (int)blockDim.x + fresh_tid()];
     const uint32_t rw[4] = {rq.x, rq.y, rq.z, rq.w};
 #pragma unroll
     for (int e = 0; e < kMaxDv; ++e) {
@@ -330,10 +339,10 @@ __device__ __forceinline__ void flip_resid(const DevGraph& g, uint32_t* resid, u
 template <int CPT, int PW>
 __device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint32_t* resid,
                                           const Res<CPT, PW>& R, RunRegs<CPT>& rg) {
-  const int B = blockDim.x;
+  const int B = blockDim.x, tid = fresh_tid();
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int j = c * B + threadIdx.x;
+    const int j = c * B + tid;
     const bool active = j < g.n && !((rg.mbits >> c) & 1u);
     uint32_t eb = 0;
     const int D = col_dmax(R, c);
@@ -371,7 +380,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
                                          uint32_t* err, const FirstIter* fi = nullptr,
                                          bool have_pf = false, uint32_t pf = 0u,
                                          const float* asched = nullptr, int nsched = 0) {
-  const int tid = threadIdx.x, B = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = fresh_tid(), B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
   const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
   rg.mbits = rg.vbits = rg.ebits = 0;
@@ -669,7 +678,7 @@ __device__ __forceinline__ void flip_write(const DevGraph& g, const Lds& L, uint
   lds_barrier();
   const unsigned long long t =
       (unsigned long long)L.u32(kOffFlips)[0] | ((unsigned long long)L.u32(kOffFlips)[1] << 32);
-  for (int r = threadIdx.x; r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
+  for (int r = fresh_tid(); r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
 }
 
 // Shot output from register-resident hard decisions (columns c*B + tid).
@@ -680,34 +689,41 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, 
                                                uint8_t* corr, uint8_t* flips, const BatchArgs& a,
                                                const Res<CPT, PW>& R, long long next_shot,
                                                long long& pf_shot, uint32_t& pf, int& work_hint) {
-  const int B = blockDim.x;
-  unsigned long long f = 0;
-  // All loads before the stores: a wait for a load also waits for every
-  // memory operation issued before it.  The logical masks (needed here) go
-  // first; the next step's loads follow and stay in flight past the wait.
+  const int B = blockDim.x, tid = fresh_tid();
+  // Every load is issued, and consumed, before the first store: a wait for a
+  // load also waits for the memory operations issued before it, so nothing
+  // waits on the stores, which drain while the next step works in LDS.
+  unsigned long long lm[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int j = c * B + threadIdx.x;
-    if (j < g.n && ((bits >> c) & 1u)) f ^= g.lmask[j];
+    const int j = c * B + tid;
+    lm[c] = (j < g.n && ((bits >> c) & 1u)) ? g.lmask[j] : 0ull;
   }
-  asm volatile("" ::: "memory");  // keep the order of issue
-  if (threadIdx.x == 0) work_hint = __hip_atomic_load(&a.st->work.count, __ATOMIC_RELAXED, AGENT);
+  int wh = work_hint;
+  if (tid == 0) wh = __hip_atomic_load(&a.st->work.count, __ATOMIC_RELAXED, AGENT);
+  uint32_t sb[2] = {0u, 0u};
   if (next_shot >= 0) {
     const uint8_t* ns = a.syn + next_shot * g.m;
-    uint32_t v = 0;
 #pragma unroll
     for (int q = 0; q < 2; ++q)
-      if (R.row[q] >> 31) v |= (uint32_t)ns[R.row[q] & 0xFFFFu] << (8 * q);
+      if (R.row[q] >> 31) sb[q] = ns[R.row[q] & 0xFFFFu];
+  }
+  unsigned long long f = 0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) f ^= lm[c];
+  uint32_t v = sb[0] | (sb[1] << 8);
+  asm volatile("" : "+v"(wh), "+v"(v), "+v"(f)::"memory");  // the loads complete here
+  work_hint = wh;
+  if (next_shot >= 0) {
     pf = v;
     pf_shot = next_shot;
   }
-  asm volatile("" ::: "memory");
+  flip_fold(L, f);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int j = c * B + threadIdx.x;
+    const int j = c * B + tid;
     if (j < g.n) corr[j] = (uint8_t)((bits >> c) & 1u);
   }
-  flip_fold(L, f);
   flip_write(g, L, flips);
 }
 
