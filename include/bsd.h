@@ -196,9 +196,11 @@ bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, in
  * Serving: requests that arrive over time are decoded continuously.
  *
  * A server keeps one persistent decoder per code running on the GPU, each on
- * its own stream with its own share of the compute units.  Codes whose BP run
- * fills a compute unit's LDS share three quarters of the units.  The other
- * codes get a few small workgroups each.  Requests pass through a ring per
+ * its own stream with its own workgroups.  By default a code whose BP run
+ * fills a compute unit's LDS gets one workgroup on each of 1/16 of the units,
+ * and any other code 2 x beam_width workgroups (at least 32): sizes for a
+ * few thousand requests per second per code, since idle workgroups poll.
+ * Heavier loads pass larger grid_blocks.  Requests pass through a ring per
  * code in pinned host memory.  The host writes the syndrome and publishes it,
  * and the decoder claims it as soon as one of its workgroups is free.  This
  * is the decoder's own work queue, so several requests of a code and the
@@ -211,8 +213,9 @@ bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, in
  * published count over the bus and mirroring it in device memory.
  * The decoders must all run at once: each needs a hardware queue of its own
  * (HIP's GPU_MAX_HW_QUEUES bounds them per process) and its compute units.
- * Creation waits until every decoder reports that it runs, else fails with
- * BSD_EDEVICE.
+ * Creation launches them one at a time, largest LDS first, and waits until
+ * every workgroup of one is resident before launching the next; a decoder
+ * that does not get there within 5 s makes creation fail with BSD_EDEVICE.
  * A server holds its codes (bsd_code_destroy returns BSD_EBUSY meanwhile).
  * Its kernels end when it is destroyed, or on their own after about 20 s
  * without work. */

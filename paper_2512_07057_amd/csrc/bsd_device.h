@@ -1130,14 +1130,18 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   load_res<CPT, PW>(a.g, L, R);
   unsigned long long nruns = 0, niters = 0;
   const int tid = threadIdx.x;
-  if (a.stream && blockIdx.x == 0 && tid == 0)
-    __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (a.stream && tid == 0) {
+    // Serving: the last workgroup to begin tells the host that all are resident.
+    const uint32_t k = __hip_atomic_fetch_add(&a.st->started_wgs, 1u, __ATOMIC_RELAXED, AGENT) + 1u;
+    if (k == gridDim.x) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
   long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
   bool exhausted = false;         // thread 0 only
   int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
   bool idling = false;            // thread 0 only, serving: in an idle stretch since idle_since
+  int backoff = 1;                // thread 0 only, serving: sleep units of the next idle pass
   uint32_t idle_since = 0;
   long long pf_shot = -1;         // shot whose syndrome bits `pf` holds (uniform)
   uint32_t pf = 0;
@@ -1224,8 +1228,13 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
           if (__hip_atomic_load(&a.st->stop, __ATOMIC_ACQUIRE, AGENT) ||
               now - idle_since > a.idle_limit)
             kind = 3;
-          else
-            __builtin_amdgcn_s_sleep(16);
+          else {
+            // Idle workgroups back off (up to about 8K cycles a pass), so
+            // that their polling does not crowd the queue counters' cache
+            // lines when a decoder has many more workgroups than requests.
+            for (int u = 0; u < backoff; ++u) __builtin_amdgcn_s_sleep(16);
+            backoff = backoff < 8 ? 2 * backoff : 8;
+          }
         } else if (__hip_atomic_load(&a.st->done, __ATOMIC_ACQUIRE, AGENT) >=
                    (unsigned long long)a.shots) {
           kind = 3;
@@ -1234,6 +1243,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
         }
       } else {
         idling = false;
+        backoff = 1;
       }
       box[0] = kind;
       box[1] = (int)item;

@@ -1233,14 +1233,12 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
   bsd_server s = new (std::nothrow) bsd_server_s;
   if (!s) return fail(BSD_ENOMEM, "host allocation failed");
   s->device = dev;
-  // Codes whose run fills a compute unit's LDS share 3/4 of the units; the
-  // others share four workgroups per remaining unit (a round of children of
-  // a deep shot then runs side by side).
-  int nbig = 0;
-  for (int i = 0; i < ncodes; ++i) nbig += codes[i]->lds > 64 * 1024;
-  const int nsmall = ncodes - nbig;
-  const int big_cus = nbig ? std::max(1, (3 * ncu / 4) / nbig) * nbig : 0;
-  const int small_grid = nsmall ? std::max(1, 4 * (ncu - big_cus) / nsmall) : 0;
+  // Automatic sizes.  Idle workgroups poll the queue counters, and on a
+  // mixed load of a few thousand requests per second per code fewer
+  // workgroups gave lower latency at every percentile: a code whose run
+  // fills a compute unit's LDS gets ncu/16 workgroups (one per unit), any
+  // other code as many as the children of one round of a deep shot
+  // (2 x beam width, at least 32), so that round runs side by side.
   const int64_t budget = ring_bytes > 0 ? ring_bytes : (int64_t)64 << 20;
   for (int i = 0; i < ncodes; ++i) {
     ServeQ& q = s->q[i];
@@ -1251,8 +1249,8 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
     q.prm = params[i];
     const bool big = c->lds > 64 * 1024;
     q.grid = grid_blocks && grid_blocks[i] > 0 ? grid_blocks[i]
-             : big ? std::max(1, (3 * ncu / 4) / std::max(1, nbig))
-                   : std::min(c->grid, small_grid);
+             : big ? std::max(1, ncu / 16)
+                   : std::min(c->grid, std::max(32, 2 * q.prm.beam_width));
     const DevGraph& g = c->g;
     const size_t per = (size_t)g.m + g.n + std::max(g.k, 1) + 1 + 8;
     uint64_t rows = 64;
@@ -1320,6 +1318,10 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
   for (int i = 0; i < ncodes; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return s->q[x].code->lds > s->q[y].code->lds; });
+  // One at a time: each kernel must have every workgroup resident before
+  // the next is launched, so that the units a large-LDS decoder needs are
+  // not taken by the small decoders' workgroups first, and no kernel waits
+  // behind another on a shared hardware queue.
   s->launched = true;
   for (int i : order) {
     ServeQ& q = s->q[i];
@@ -1330,25 +1332,17 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
       server_free(s);
       return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
     }
-  }
-  // Every kernel must be running at once (none may wait behind another on a
-  // shared hardware queue or for compute units): wait for each to report.
-  const double t0 = now_us();
-  for (;;) {
-    bool all = true;
-    for (int i = 0; i < ncodes; ++i) all = all && __atomic_load_n(s->q[i].started, __ATOMIC_ACQUIRE) != 0;
-    if (all) break;
-    if (now_us() - t0 > 5e6) {
-      std::string which;
-      for (int i = 0; i < ncodes; ++i)
-        if (!__atomic_load_n(s->q[i].started, __ATOMIC_ACQUIRE)) which += " decoder" + std::to_string(i);
-      const bsd_status st = server_stop(s);
-      if (st == BSD_OK) server_free(s);
-      return fail(BSD_EDEVICE, "serving kernels did not all start within 5 s (not running:%s); "
-                  "more hardware queues (GPU_MAX_HW_QUEUES) or fewer workgroups may be needed",
-                  which.c_str());
+    const double t0 = now_us();
+    while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
+      if (now_us() - t0 > 5e6) {
+        const bsd_status st = server_stop(s);
+        if (st == BSD_OK) server_free(s);
+        return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every workgroup "
+                    "running within 5 s; more hardware queues (GPU_MAX_HW_QUEUES) or fewer "
+                    "workgroups may be needed", i, q.grid);
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(100));
     }
-    std::this_thread::sleep_for(std::chrono::microseconds(100));
   }
   *out = s;
   return BSD_OK;

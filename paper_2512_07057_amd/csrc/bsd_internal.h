@@ -92,7 +92,7 @@ struct BatchState {
   unsigned long long iterations;
   unsigned long long deep;
   uint32_t error;
-  uint32_t pad;
+  uint32_t started_wgs;  // serving: workgroups of the launch that have begun
   Ring work;
   Ring ctxq;
   // Serving: mirrors of the host's published count and stop flag, refreshed
@@ -144,7 +144,7 @@ struct BatchArgs {
   const unsigned long long* pub_host;  // host memory: shots published
   const uint32_t* stop_host;           // host memory: nonzero ends the kernel
   uint32_t* done_flag;         // per row: low 32 bits of shot + 1 once its outputs are written
-  uint32_t* started;           // host memory: set to 1 when the kernel's first workgroup runs
+  uint32_t* started;           // host memory: set to 1 once every workgroup of the launch runs
   uint32_t idle_limit;         // also end after this many 100 MHz ticks with nothing to do
   long long shots;
   const uint8_t* syn;

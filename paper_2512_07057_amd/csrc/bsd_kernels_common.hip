@@ -17,6 +17,7 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->iterations = 0;
     a.st->deep = 0;
     a.st->error = 0;
+    a.st->started_wgs = 0;
     a.st->work.head = 0;
     a.st->work.tail = 0;
     a.st->work.count = 0;
