@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--plain-shots", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-buffers", action="store_true",
+                    help="skip the host-buffer (bus-inclusive) leg, e.g. under a profiler")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-loop measurement (Poisson arrivals over W0/W1/W2)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -202,10 +204,12 @@ def main():
 
     # The same decode from host buffers (syndromes in and results out over
     # the bus, staged by the library): the bus-inclusive rate.
-    code.decode_host(syn_h[:1000], prm)
-    th = time.perf_counter()
-    code.decode_host(syn_h, prm)
-    host_rate = shots / (time.perf_counter() - th)
+    host_rate = None
+    if not args.no_host_buffers:
+        code.decode_host(syn_h[:1000], prm)
+        th = time.perf_counter()
+        code.decode_host(syn_h, prm)
+        host_rate = shots / (time.perf_counter() - th)
 
     # Plain form: one kernel launch per BP run, beam bookkeeping on the host.
     nplain = min(args.plain_shots, shots)
