@@ -136,6 +136,20 @@ struct RunRes {
   int cancelled;
 };
 
+// Loads a persistent workgroup issues during a shot's initial run for the
+// step after it, so that they complete while the run computes instead of on
+// the way out: the next shot's syndrome bits (after the prologue), the
+// logical mask of each lane's lowest set hard decision and the work queue's
+// length (after each variable phase).  Values are consumed only on output.
+struct EarlyLoads {
+  const uint8_t* next_syn;          // next shot's syndrome, or nullptr
+  const int32_t* work_count;        // read by thread 0
+  const uint64_t* lmask;            // [n] logical masks
+  uint32_t sb[2];                   // out: syndrome bytes of the lane's row slots
+  int32_t work_hint;                // out, thread 0
+  unsigned long long lm;            // out: lmask of the lowest set bit of ebits, else 0
+};
+
 template <int CPT, int PW>
 __device__ __forceinline__ int col_deg(const Res<CPT, PW>& R, int c) {
   return (int)((R.deg[c >> 3] >> (4 * (c & 7))) & 15u);
@@ -379,7 +393,8 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
                                          const int32_t* cancel, int my_gen, RunRegs<CPT>& rg,
                                          uint32_t* err, const FirstIter* fi = nullptr,
                                          bool have_pf = false, uint32_t pf = 0u,
-                                         const float* asched = nullptr, int nsched = 0) {
+                                         const float* asched = nullptr, int nsched = 0,
+                                         EarlyLoads* early = nullptr) {
   const int tid = fresh_tid(), B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
   const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
@@ -494,6 +509,14 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
     }
     lds_barrier();
   }
+  if (early) {
+    early->sb[0] = early->sb[1] = 0u;
+    if (early->next_syn) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (R.row[q] >> 31) early->sb[q] = early->next_syn[R.row[q] & 0xFFFFu];
+    }
+  }
 
   RunRes rr{0, 0, 0};
   for (int t = 1; t <= T; ++t) {
@@ -511,6 +534,11 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
       lds_barrier();
     }
     var_phase<CPT, PW>(g, L, resid, R, rg);
+    if (early) {
+      const uint32_t eb = rg.ebits & ~rg.mbits;
+      early->lm = eb ? early->lmask[__builtin_ctz(eb) * B + tid] : 0ull;
+      if (tid == 0) early->work_hint = __hip_atomic_load(early->work_count, __ATOMIC_RELAXED, AGENT);
+    }
     if (tid == 0) {
       int cx = 0;
       if (cancel) cx = __hip_atomic_load(cancel, __ATOMIC_RELAXED, AGENT) < my_gen;
@@ -681,43 +709,24 @@ __device__ __forceinline__ void flip_write(const DevGraph& g, const Lds& L, uint
   for (int r = fresh_tid(); r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
 }
 
-// Shot output from register-resident hard decisions (columns c*B + tid).
-// Also issues the loads the next step needs: the syndrome bits of the next
-// shot this workgroup starts and the length of the work queue.
+// Shot output from register-resident hard decisions (columns c*B + tid),
+// with the loads the run issued early (EarlyLoads): the logical masks, the
+// next shot's syndrome bits and the work queue's length.  Only a lane with
+// more than one set decision loads here.
 template <int CPT, int PW>
 __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, uint32_t bits,
-                                               uint8_t* corr, uint8_t* flips, const BatchArgs& a,
-                                               const Res<CPT, PW>& R, long long next_shot,
+                                               uint8_t* corr, uint8_t* flips,
+                                               const EarlyLoads& el, long long next_shot,
                                                long long& pf_shot, uint32_t& pf, int& work_hint) {
   const int B = blockDim.x, tid = fresh_tid();
-  // Every load is issued, and consumed, before the first store: a wait for a
-  // load also waits for the memory operations issued before it, so nothing
-  // waits on the stores, which drain while the next step works in LDS.
-  unsigned long long lm[CPT];
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int j = c * B + tid;
-    lm[c] = (j < g.n && ((bits >> c) & 1u)) ? g.lmask[j] : 0ull;
-  }
-  int wh = work_hint;
-  if (tid == 0) wh = __hip_atomic_load(&a.st->work.count, __ATOMIC_RELAXED, AGENT);
-  uint32_t sb[2] = {0u, 0u};
+  unsigned long long f = el.lm;
+  for (uint32_t mk = bits & (bits - 1u); mk; mk &= mk - 1u) f ^= g.lmask[__builtin_ctz(mk) * B + tid];
+  if (tid == 0) work_hint = el.work_hint;
   if (next_shot >= 0) {
-    const uint8_t* ns = a.syn + next_shot * g.m;
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (R.row[q] >> 31) sb[q] = ns[R.row[q] & 0xFFFFu];
-  }
-  unsigned long long f = 0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) f ^= lm[c];
-  uint32_t v = sb[0] | (sb[1] << 8);
-  asm volatile("" : "+v"(wh), "+v"(v), "+v"(f)::"memory");  // the loads complete here
-  work_hint = wh;
-  if (next_shot >= 0) {
-    pf = v;
+    pf = el.sb[0] | (el.sb[1] << 8);
     pf_shot = next_shot;
   }
+  asm volatile("" : "+v"(f)::"memory");  // every load completes before the stores
   flip_fold(L, f);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -983,17 +992,23 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   const uint32_t t0 = (a.lat && threadIdx.x < 64) ? dev_clock() : 0u;
   RunRegs<CPT> rg;
   const long long row = io_row(a, shot);
+  EarlyLoads el;
+  el.next_syn = next_shot >= 0 ? a.syn + next_shot * g.m : nullptr;
+  el.work_count = &a.st->work.count;
+  el.lmask = g.lmask;
+  el.work_hint = -1;
+  el.lm = 0ull;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + row * g.m,
                                     a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
-                                    &a.fi, pf_shot == shot, pf, a.alpha_sched, a.n_sched);
+                                    &a.fi, pf_shot == shot, pf, a.alpha_sched, a.n_sched, &el);
   pf_shot = -1;
   nruns += 1;
   niters += rr.iters;
   const bool many = a.num_results > 1;
   if ((rr.conv && !many) || a.max_rounds == 0) {
-    // Read the work queue's length now: the load completes while the shot is
-    // written out, and the next scheduling step skips the queue when empty.
-    emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, a, R,
+    // The work queue's length was read during the run: the next scheduling
+    // step skips the queue when it was empty.
+    emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, el,
                             next_shot, pf_shot, pf, work_hint);
     if (threadIdx.x == 0) {
       a.conv[row] = (uint8_t)rr.conv;
