@@ -457,15 +457,31 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
           mu[pq] = (k == argk ? y : x) | (sg ^ nb);
         }
       } else {
+        // Every edge gets x, then the edge of the least |Lambda| gets y: a
+        // lane's LDS writes land in program order.
+        const uint32_t xs = x | sg;
         int k = 0;
+        for (; k + 8 <= dg; k += 8) {
+          const int4 d0 = *reinterpret_cast<const int4*>(diag + k);
+          const int4 d1 = *reinterpret_cast<const int4*>(diag + k + 4);
+          mu[d0.x + r] = xs;
+          mu[d0.y + r] = xs;
+          mu[d0.z + r] = xs;
+          mu[d0.w + r] = xs;
+          mu[d1.x + r] = xs;
+          mu[d1.y + r] = xs;
+          mu[d1.z + r] = xs;
+          mu[d1.w + r] = xs;
+        }
         for (; k + 4 <= dg; k += 4) {
           const int4 dd = *reinterpret_cast<const int4*>(diag + k);
-          mu[dd.x + r] = (k == argk ? y : x) | sg;
-          mu[dd.y + r] = (k + 1 == argk ? y : x) | sg;
-          mu[dd.z + r] = (k + 2 == argk ? y : x) | sg;
-          mu[dd.w + r] = (k + 3 == argk ? y : x) | sg;
+          mu[dd.x + r] = xs;
+          mu[dd.y + r] = xs;
+          mu[dd.z + r] = xs;
+          mu[dd.w + r] = xs;
         }
-        for (; k < dg; ++k) mu[diag[k] + r] = (k == argk ? y : x) | sg;
+        for (; k < dg; ++k) mu[diag[k] + r] = xs;
+        if (argk < dg) mu[diag[argk] + r] = y | sg;
       }
     }
   } else if (parent) {
