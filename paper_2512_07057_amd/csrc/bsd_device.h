@@ -220,12 +220,15 @@ __device__ __forceinline__ void load_res(const DevGraph& g, const Lds& L, Res<CP
 }
 
 // Running least and second least magnitude: m1 <= m2 and |v| joins them.
-// The median of (m1, m2, |v|) is the new second least.  fmed3 takes the
-// absolute value as a free source modifier.
-__device__ __forceinline__ void min2_step(float& m1, float& m2, uint32_t v) {
+// The median of (m1, m2, |v|) is the new second least, the median of
+// (m1, |v|, -inf) the new least.  fmed3 takes the absolute value as a free
+// source modifier.  `ninf` is -inf passed in a register: with the constant
+// visible the compiler turns the second median into an IEEE minimum, which
+// costs two extra canonicalising instructions per edge.
+__device__ __forceinline__ void min2_step(float& m1, float& m2, uint32_t v, float ninf) {
   const float a = fabsf(__uint_as_float(v));
   m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
-  m1 = __builtin_amdgcn_fmed3f(m1, a, -__builtin_inff());
+  m1 = __builtin_amdgcn_fmed3f(m1, a, ninf);
 }
 
 // Output of eq. (1) on one edge holding v: magnitude d2 if |v| is the row
@@ -258,6 +261,8 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
   const uint32_t zp = zero_pos(g);
   uint32_t sgn = dg ? ((L.sprime()[r >> 5] >> (r & 31)) & 1u) << 31 : 0u;
   float m1 = kLlrMax, m2 = kLlrMax;
+  float ninf = -__builtin_inff();
+  asm volatile("" : "+v"(ninf));
   int k = 0;
   for (; k + 4 <= kmin; k += 4) {
     const int4 dd = *reinterpret_cast<const int4*>(diag + k);
@@ -265,14 +270,14 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       sgn ^= vv[u];
-      min2_step(m1, m2, vv[u]);
+      min2_step(m1, m2, vv[u], ninf);
     }
   }
   for (; k < kmax; ++k) {
     const bool ok = k < dg;
     const uint32_t v = msg[ok ? (uint32_t)(diag[k] + r) : zp];
     sgn ^= v;
-    min2_step(m1, m2, ok ? v : kInfBits);
+    min2_step(m1, m2, ok ? v : kInfBits, ninf);
   }
   const float d1 = fminf(alpha * m1, kLlrMax), d2 = fminf(alpha * m2, kLlrMax);
   k = 0;
