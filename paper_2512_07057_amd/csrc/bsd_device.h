@@ -412,7 +412,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
       rg.vbits |= (uint32_t)(pv & 1) << (d / B);
     }
   }
-  if (tid < 4) L.u32(kOffFlips)[tid] = 0u;
+  if (tid < 2) L.u32(kOffFlips)[tid] = 0u;
   // s by row rank, 64 ranks per wave ballot.  A table run also fills the
   // residual of iteration 1 here (s' = s without masked nodes).
   uint32_t sbit[2];
@@ -531,6 +531,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
     lds_barrier();
   }
   if (early) {
+    if (tid < 2) L.u32(kOffFlips)[2 + tid] = 0u;  // read by everyone before the barrier above
     early->sb[0] = early->sb[1] = 0u;
     if (early->next_syn) {
 #pragma unroll
@@ -716,10 +717,24 @@ __device__ __forceinline__ void store_msg(const DevGraph& g, const Lds& L, float
 // Logical flips A e-hat: lanes holding a 1 fold their column's mask into an
 // LDS accumulator (zeroed at the start of every run); one barrier, then the
 // bytes are written.
-__device__ __forceinline__ void flip_fold(const Lds& L, unsigned long long f) {
+__device__ __forceinline__ void flip_fold(const Lds& L, unsigned long long f, int w = 0) {
   if (f) {
-    atomicXor(&L.u32(kOffFlips)[0], (uint32_t)f);
-    atomicXor(&L.u32(kOffFlips)[1], (uint32_t)(f >> 32));
+    atomicXor(&L.u32(kOffFlips)[w], (uint32_t)f);
+    atomicXor(&L.u32(kOffFlips)[w + 1], (uint32_t)(f >> 32));
+  }
+}
+
+// Batched calls fold an initial run's flips into the second accumulator
+// (words 2 and 3) and write them out only after the next scheduling
+// barrier, which saves the output step a barrier of its own.  The words are
+// cleared by the next initial run after its prologue barrier, once every
+// lane has read them.
+__device__ __forceinline__ void flip_write_late(const DevGraph& g, const Lds& L, uint8_t* flips) {
+  const int tid = fresh_tid();
+  if (tid < g.k) {
+    const unsigned long long t =
+        (unsigned long long)L.u32(kOffFlips)[2] | ((unsigned long long)L.u32(kOffFlips)[3] << 32);
+    for (int r = tid; r < g.k; r += blockDim.x) flips[r] = (uint8_t)((t >> r) & 1ull);
   }
 }
 
@@ -738,7 +753,8 @@ template <int CPT, int PW>
 __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, uint32_t bits,
                                                uint8_t* corr, uint8_t* flips,
                                                const EarlyLoads& el, long long next_shot,
-                                               long long& pf_shot, uint32_t& pf, int& work_hint) {
+                                               long long& pf_shot, uint32_t& pf, int& work_hint,
+                                               bool late_flips) {
   const int B = blockDim.x, tid = fresh_tid();
   unsigned long long f = el.lm;
   for (uint32_t mk = bits & (bits - 1u); mk; mk &= mk - 1u) f ^= g.lmask[__builtin_ctz(mk) * B + tid];
@@ -748,19 +764,19 @@ __device__ __forceinline__ void emit_from_regs(const DevGraph& g, const Lds& L, 
     pf_shot = next_shot;
   }
   asm volatile("" : "+v"(f)::"memory");  // every load completes before the stores
-  flip_fold(L, f);
+  flip_fold(L, f, late_flips ? 2 : 0);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int j = c * B + tid;
     if (j < g.n) corr[j] = (uint8_t)((bits >> c) & 1u);
   }
-  flip_write(g, L, flips);
+  if (!late_flips) flip_write(g, L, flips);
 }
 
 // Shot output from a global bit-vector.
 __device__ __forceinline__ void emit_from_bits(const DevGraph& g, const Lds& L,
                                                const uint32_t* bits, uint8_t* corr, uint8_t* flips) {
-  if (threadIdx.x < 4) L.u32(kOffFlips)[threadIdx.x] = 0u;
+  if (threadIdx.x < 2) L.u32(kOffFlips)[threadIdx.x] = 0u;
   lds_barrier();
   unsigned long long f = 0;
   for (int j = threadIdx.x; j < g.n; j += blockDim.x) {
@@ -1006,7 +1022,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
                                              Res<CPT, PW>& R, long long shot, int ctx,
                                              unsigned long long& nruns, unsigned long long& niters,
                                              int& work_hint, long long next_shot, long long& pf_shot,
-                                             uint32_t& pf) {
+                                             uint32_t& pf, long long& flips_row) {
   const DevGraph& g = a.g;
   // The clock is read only when latencies are asked for, by one wave: the
   // read returns on the same counter as LDS operations.
@@ -1030,7 +1046,8 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     // The work queue's length was read during the run: the next scheduling
     // step skips the queue when it was empty.
     emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, el,
-                            next_shot, pf_shot, pf, work_hint);
+                            next_shot, pf_shot, pf, work_hint, !a.stream);
+    if (!a.stream) flips_row = row;  // written after the next scheduling barrier
     if (threadIdx.x == 0) {
       a.conv[row] = (uint8_t)rr.conv;
       if (a.lat) a.lat[row] = dev_clock() - t0;
@@ -1181,6 +1198,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   uint32_t idle_since = 0;
   long long pf_shot = -1;         // shot whose syndrome bits `pf` holds (uniform)
   uint32_t pf = 0;
+  long long flips_row = -1;       // output row whose flips wait in the second accumulator
   int32_t* misc = L.misc();
   for (int it = 0;; ++it) {
     opaque_res<CPT, PW>(R);
@@ -1295,10 +1313,14 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
     const uint32_t item = (uint32_t)box[1];
     const long long shot = (long long)(uint32_t)box[2] | ((long long)box[3] << 32);
     const long long next_shot = (long long)(uint32_t)box[4] | ((long long)box[5] << 32);
+    if (flips_row >= 0) {
+      flip_write_late(a.g, L, a.flips + flips_row * a.g.k);
+      flips_row = -1;
+    }
     if (kind == 3) break;
     if (kind == 2) {
       if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters, work_hint, next_shot,
-                                pf_shot, pf) &&
+                                pf_shot, pf, flips_row) &&
           tid == 0)
         spare = -1;
     } else if (kind == 1) {
