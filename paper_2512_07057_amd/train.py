@@ -1,5 +1,5 @@
 """Learn per-iteration scalings alpha_t and prior LLRs with the differentiable
-unrolled min-sum decoder, then judge them by the beam decoder's logical
+unrolled min-sum decoder, then evaluate them by the beam decoder's logical
 error rate.
 
 Training: T flooding iterations (default 25) on batches of freshly sampled
@@ -85,7 +85,7 @@ def main(argv=None):
             print(f"step {step} loss {losses[-1]:.6f}", file=sys.stderr, flush=True)
     train_s = time.perf_counter() - t0
 
-    # Judge by the beam decoder at beam width 8.
+    # Evaluate with the beam decoder at beam width 8.
     ev = sampler.sample(pr, args.eval_shots, 0)
     syn = torch.from_numpy(ev["syndromes"]).cuda()
     P = workloads.params_100iters(8)
