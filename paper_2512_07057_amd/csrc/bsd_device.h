@@ -13,9 +13,10 @@
 // warm-start messages and its results.
 //
 // LDS layout: a fixed 7072-byte area of small arrays at offset 0 (constant
-// offsets), then the messages, then one trash word per lane that absorbs
-// stores of absent edges and one word of 0.0 that loads of absent edges
-// read, so the inner loops need no branches.
+// offsets), then the messages, then one word of 0.0 per lane that a
+// column's absent edges load from and store 0.0 back to (variable phase),
+// and one shared word of 0.0 for absent row slots (check phase), so the
+// inner loops need no branches.
 //
 // Floating-point order follows the paper's formulas left to right: sums run
 // over neighbours in ascending row index, E of eq. (2) is a literal exclusive
@@ -66,8 +67,8 @@ struct Lds {
   __device__ __forceinline__ uint32_t* resid(int b) const { return u32(kOffResid + 256 * b); }
 };
 
-// After the messages: one trash word per lane that takes stores of absent
-// edges (never read), then one word that stays 0.0 (loads of absent edges).
+// After the messages: one word per lane for a column's absent edges, then
+// one word for absent row slots; all stay 0.0.
 __host__ __device__ inline size_t lds_need(const DevGraph& g) {
   return (size_t)kOffMsg + ((size_t)g.nnz_pad + kTrashWords + 4) * 4;
 }
@@ -186,7 +187,10 @@ __device__ __forceinline__ void load_res(const DevGraph& g, const Lds& L, Res<CP
   const int tid = threadIdx.x, B = blockDim.x;
   for (int i = tid; i < 256; i += B) L.i32(kOffDiag)[i] = i <= g.maxdeg_row ? g.diag_ptr[i] : 0;
   if (tid == 0) L.msg()[zero_pos(g)] = 0.f;
-  const uint32_t tp = zero_pos(g);
+  if (tid < kTrashWords) L.msg()[g.nnz_pad + tid] = 0.f;
+  // Absent edges of a column point at the lane's own word after the
+  // messages (kept at 0.0: the variable phase writes back what it read).
+  const uint32_t tp = trash_pos(g);
 #pragma unroll
   for (int w = 0; w < (CPT + 7) / 8; ++w) R.deg[w] = R.dmx[w] = 0u;
 #pragma unroll
@@ -299,8 +303,8 @@ __device__ __forceinline__ void check_rows(const DevGraph& g, const Lds& L, uint
 }
 
 // Eqs. (2)-(4) for one column with at most D edges (D uniform over the wave).
-// Absent edges read the zero word; their stores, and all stores of inactive
-// lanes (masked nodes, columns past n), go to the lane's trash word.
+// Absent edges load from and store to the lane's own zero word; inactive
+// lanes (masked nodes, columns past n) store back the values they loaded.
 template <int D, int CPT, int PW>
 __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
                                         int c, bool active, float& sl, uint32_t& eb) {
@@ -308,7 +312,6 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const R
   uint32_t dw = R.deg[c >> 3];
   asm volatile("" : "+v"(dw));
   const int dg = (int)((dw >> (4 * (c & 7))) & 15u);
-  const uint32_t tp = trash_pos(g);
   uint32_t p[D];
   float d[D];
   // Unpack the positions here, inside the iteration: kept packed across
@@ -323,7 +326,6 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const R
   for (int e = 0; e < D; ++e) {
     p[e] = (pk[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
     d[e] = msg[p[e]];
-    p[e] = (active && e < dg) ? p[e] : tp;
   }
   float pre = R.lam[c];
 #pragma unroll
@@ -331,7 +333,9 @@ __device__ __forceinline__ void var_col(const DevGraph& g, const Lds& L, const R
     float x = pre;
 #pragma unroll
     for (int f = e + 1; f < D; ++f) x = x + d[f];
-    msg[p[e]] = __builtin_amdgcn_fmed3f(x, -kLlrMax, kLlrMax);
+    // Absent edges (lane's zero word) and inactive lanes write back what
+    // they read: one address per edge for the load and the store.
+    msg[p[e]] = (active && e < dg) ? __builtin_amdgcn_fmed3f(x, -kLlrMax, kLlrMax) : d[e];
     pre = pre + d[e];
   }
   const float post = pre;  // eq. (3)
