@@ -1297,7 +1297,11 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
                    (unsigned long long)a.shots) {
           kind = 3;
         } else {
-          __builtin_amdgcn_s_sleep(8);
+          // Waiting for child runs of deep shots: back off too (up to about
+          // 4K cycles a pass), as thousands of small workgroups polling the
+          // same counters slow down the atomics of the busy ones.
+          for (int u = 0; u < backoff; ++u) __builtin_amdgcn_s_sleep(8);
+          backoff = backoff < 8 ? 2 * backoff : 8;
         }
       } else {
         idling = false;

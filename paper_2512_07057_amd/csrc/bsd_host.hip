@@ -777,14 +777,16 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   for (int j = 0; j < n; ++j) maxdeg_col = std::max(maxdeg_col, h_colptr[j + 1] - h_colptr[j]);
   c->pw = (maxdeg_col + 1) / 2;
   // A workgroup of 1024 lanes holds up to 9 columns per lane in registers;
-  // beyond that 512 lanes get twice the registers.  Small graphs share a CU
-  // between many single-wave workgroups.  BSD_BLOCK overrides the choice;
-  // bsd_code_autotune measures.
+  // beyond that 512 lanes get twice the registers.  Small graphs get 512-lane
+  // workgroups, two per CU: with thousands of single-wave workgroups, the
+  // idle ones' polling of the queue counters slowed the busy ones' atomics
+  // (W0, W1 and the XYZ workload ran 1.3 to 4.7 times slower).  BSD_BLOCK
+  // overrides the choice; bsd_code_autotune measures.
   int block;
   if (c->lds > 64 * 1024) {
     block = supported_cpt((n + 1023) / 1024) <= 9 ? 1024 : 512;
   } else {
-    block = 64;
+    block = 512;
     while (supported_cpt((n + block - 1) / block) > 16 || m > 2 * block) block *= 2;
   }
   if (const char* eb = getenv("BSD_BLOCK")) {
