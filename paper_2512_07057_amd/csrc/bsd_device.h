@@ -852,7 +852,8 @@ __device__ __forceinline__ void finish_deep(const BatchArgs& a, const Lds& L, in
     if (a.lat) a.lat[row] = dev_clock() - t_start;
   }
   publish_done(a, shot);
-  __threadfence();
+  // The barrier orders every lane's writes before thread 0's release in
+  // ring_push, which publishes them at device scope.
   __syncthreads();
   if (threadIdx.x == 0) {
     ring_push(&a.st->ctxq, a.ctx_ring, (uint32_t)ctx);
@@ -1084,8 +1085,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     C->parent_next_pos[0] = next_pos;
     __hip_atomic_fetch_add(&a.st->deep, 1ull, __ATOMIC_RELAXED, AGENT);
   }
-  __threadfence();
-  __syncthreads();
+  __syncthreads();  // then thread 0's releasing push publishes every lane's slot writes
   if (threadIdx.x == 0) {
     ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 0u);
     ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 1u);
@@ -1112,8 +1112,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
     misc[14] = C->shot;
     misc[15] = __hip_atomic_load(&C->best_gen, __ATOMIC_RELAXED, AGENT) < c;
   }
-  __syncthreads();
-  __threadfence();
+  __syncthreads();  // every lane's reads follow thread 0's acquire
   const int ps = misc[11], ms = misc[12], npos = misc[13], skip = misc[15];
   const long long shot = misc[14];
   char* pslot = slot_ptr(a, ctx, ps);
@@ -1161,8 +1160,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
     }
   }
   if (tid == 0) C->child_state[c] = state;
-  __threadfence();
-  __syncthreads();
+  __syncthreads();  // then thread 0's acquire-release decrement publishes every lane's writes
   if (tid == 0) {
     const int left = __hip_atomic_fetch_add(&C->pending, -1, __ATOMIC_ACQ_REL, AGENT);
     misc[16] = (left == 1);
@@ -1170,10 +1168,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
   __syncthreads();
   const int last = misc[16];
   __syncthreads();
-  if (last) {
-    __threadfence();
-    select_round(a, L, ctx);
-  }
+  if (last) select_round(a, L, ctx);  // after thread 0's acquire and two barriers
 }
 
 // Persistent batched decoder.  Each workgroup holds one spare context for
