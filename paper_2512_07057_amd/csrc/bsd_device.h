@@ -796,9 +796,11 @@ __device__ __forceinline__ void emit_from_bits(const DevGraph& g, const Lds& L,
 // Device queues: multi-producer multi-consumer rings of 32-bit items
 // ---------------------------------------------------------------------------
 
+// The count only reserves items; the data an item refers to is published by
+// the release store of its ring entry and taken by the acquire load of it.
 __device__ __forceinline__ bool ring_pop(Ring* r, uint32_t* buf, uint32_t* out) {
   if (__hip_atomic_load(&r->count, __ATOMIC_RELAXED, AGENT) <= 0) return false;
-  const int c = __hip_atomic_fetch_add(&r->count, -1, __ATOMIC_ACQ_REL, AGENT);
+  const int c = __hip_atomic_fetch_add(&r->count, -1, __ATOMIC_RELAXED, AGENT);
   if (c <= 0) {
     __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELAXED, AGENT);
     return false;
@@ -815,7 +817,7 @@ __device__ __forceinline__ void ring_push(Ring* r, uint32_t* buf, uint32_t item)
   const uint32_t t = __hip_atomic_fetch_add(&r->tail, 1u, __ATOMIC_RELAXED, AGENT) & (r->cap - 1u);
   while (__hip_atomic_load(&buf[t], __ATOMIC_RELAXED, AGENT) != 0u) __builtin_amdgcn_s_sleep(2);
   __hip_atomic_store(&buf[t], item + 1u, __ATOMIC_RELEASE, AGENT);
-  __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELEASE, AGENT);
+  __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELAXED, AGENT);
 }
 
 __device__ __forceinline__ char* slot_ptr(const BatchArgs& a, int ctx, int s) {
@@ -933,8 +935,7 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
       ++nres;
       if (nres >= a.num_results) break;
     }
-    __threadfence();
-    __syncthreads();
+    __syncthreads();  // thread 0's later releases publish every lane's result writes
     if (tid == 0) C->nresults = nres;
     if (nres >= a.num_results) {
       finish_lightest(a, L, ctx, shot, nres, t0);
@@ -1103,8 +1104,7 @@ __device__ __forceinline__ void process_child(const BatchArgs& a, const Lds& L,
   Ctx* C = a.ctxs + ctx;
   const int tid = threadIdx.x;
   int32_t* misc = L.misc();
-  if (tid == 0) {
-    __threadfence();
+  if (tid == 0) {  // the pop of `item` acquired what the round's selection released
     misc[10] = C->nset;
     misc[11] = C->slots[c >> 1];
     misc[12] = C->slots[C->nset + c];
