@@ -797,7 +797,9 @@ __device__ __forceinline__ void emit_from_bits(const DevGraph& g, const Lds& L,
 // ---------------------------------------------------------------------------
 
 // The count only reserves items; the data an item refers to is published by
-// the release store of its ring entry and taken by the acquire load of it.
+// the release of its ring entry (a release store, or a release fence before
+// a batch of relaxed stores) and taken by one acquire fence after the entry
+// has been seen.
 __device__ __forceinline__ bool ring_pop(Ring* r, uint32_t* buf, uint32_t* out) {
   if (__hip_atomic_load(&r->count, __ATOMIC_RELAXED, AGENT) <= 0) return false;
   const int c = __hip_atomic_fetch_add(&r->count, -1, __ATOMIC_RELAXED, AGENT);
@@ -807,16 +809,21 @@ __device__ __forceinline__ bool ring_pop(Ring* r, uint32_t* buf, uint32_t* out) 
   }
   const uint32_t h = __hip_atomic_fetch_add(&r->head, 1u, __ATOMIC_RELAXED, AGENT) & (r->cap - 1u);
   uint32_t x;
-  while ((x = __hip_atomic_load(&buf[h], __ATOMIC_ACQUIRE, AGENT)) == 0u) __builtin_amdgcn_s_sleep(2);
+  while ((x = __hip_atomic_load(&buf[h], __ATOMIC_RELAXED, AGENT)) == 0u) __builtin_amdgcn_s_sleep(2);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __hip_atomic_store(&buf[h], 0u, __ATOMIC_RELAXED, AGENT);
   *out = x - 1u;
   return true;
 }
 
-__device__ __forceinline__ void ring_push(Ring* r, uint32_t* buf, uint32_t item) {
+// `fenced`: the caller has issued a release fence since its last writes.
+__device__ __forceinline__ void ring_push(Ring* r, uint32_t* buf, uint32_t item, bool fenced = false) {
   const uint32_t t = __hip_atomic_fetch_add(&r->tail, 1u, __ATOMIC_RELAXED, AGENT) & (r->cap - 1u);
   while (__hip_atomic_load(&buf[t], __ATOMIC_RELAXED, AGENT) != 0u) __builtin_amdgcn_s_sleep(2);
-  __hip_atomic_store(&buf[t], item + 1u, __ATOMIC_RELEASE, AGENT);
+  if (fenced)
+    __hip_atomic_store(&buf[t], item + 1u, __ATOMIC_RELAXED, AGENT);
+  else
+    __hip_atomic_store(&buf[t], item + 1u, __ATOMIC_RELEASE, AGENT);
   __hip_atomic_fetch_add(&r->count, 1, __ATOMIC_RELAXED, AGENT);
 }
 
@@ -999,11 +1006,11 @@ __device__ __forceinline__ void select_round(const BatchArgs& a, const Lds& L, i
       C->round = round + 1;
       C->best_gen = 0x7FFFFFFF;
       C->pending = 2 * nbranch;
-      __threadfence();
+      __threadfence();  // one release for the whole batch of pushes
       for (int q = 0; q < ns; ++q)
         if (C->parent_next_pos[q] >= 0) {
-          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q));
-          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q + 1));
+          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q), true);
+          ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | (uint32_t)(2 * q + 1), true);
         }
     }
   }
@@ -1086,10 +1093,11 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     C->parent_next_pos[0] = next_pos;
     __hip_atomic_fetch_add(&a.st->deep, 1ull, __ATOMIC_RELAXED, AGENT);
   }
-  __syncthreads();  // then thread 0's releasing push publishes every lane's slot writes
+  __syncthreads();  // then thread 0's release publishes every lane's slot writes
   if (threadIdx.x == 0) {
-    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 0u);
-    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 1u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 0u, true);
+    ring_push(&a.st->work, a.work_ring, ((uint32_t)ctx << 8) | 1u, true);
   }
   return true;
 }
