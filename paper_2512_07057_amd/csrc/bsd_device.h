@@ -149,6 +149,8 @@ struct EarlyLoads {
   uint32_t sb[2];                   // out: syndrome bytes of the lane's row slots
   int32_t work_hint;                // out, thread 0
   unsigned long long lm;            // out: lmask of the lowest set bit of ebits, else 0
+  const FirstIter* fi;              // first-iteration table for the next shot, or nullptr
+  uint4 rt[2];                      // out: its entries for the lane's row slots
 };
 
 template <int CPT, int PW>
@@ -385,6 +387,60 @@ __device__ __forceinline__ void var_phase(const DevGraph& g, const Lds& L, uint3
   flip_resid(g, resid, rg.ebits);
 }
 
+// D(1) on the edges of the lane's rows (ranks q * B + tid) from the
+// first-iteration table entries `rt` and the rows' syndrome bits.
+template <int CPT, int PW>
+__device__ __forceinline__ void write_d1(const DevGraph& g, const Lds& L, const Res<CPT, PW>& R,
+                                         const FirstIter* fi, const uint4* rt,
+                                         const uint32_t* sbit) {
+  const int tid = fresh_tid(), B = blockDim.x;
+  // Magnitude y on the edge of the least |Lambda|, x elsewhere; sign
+  // (-1)^{s_i} times the parity of the other edges' priors.
+  const int32_t* diag = L.i32(kOffDiag);
+  uint32_t* mu = L.msgu();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = q * B + tid;
+    const int dg = (int)((R.row[q] >> 16) & 0xFFu);
+    const uint32_t x = rt[q].x, y = rt[q].y, info = rt[q].z;
+    const int argk = (int)(info & 0xFFu);
+    const uint32_t sg = (((info >> 8) & 1u) ^ sbit[q]) << 31;
+    if ((info >> 9) & 1u) {  // some prior of the row is negative
+      for (int k = 0; k < dg; ++k) {
+        const int pq = diag[k] + r;
+        const uint32_t nb = ((fi->negbits[pq >> 5] >> (pq & 31)) & 1u) << 31;
+        mu[pq] = (k == argk ? y : x) | (sg ^ nb);
+      }
+    } else {
+      // Every edge gets x, then the edge of the least |Lambda| gets y: a
+      // lane's LDS writes land in program order.
+      const uint32_t xs = x | sg;
+      int k = 0;
+      for (; k + 8 <= dg; k += 8) {
+        const int4 d0 = *reinterpret_cast<const int4*>(diag + k);
+        const int4 d1 = *reinterpret_cast<const int4*>(diag + k + 4);
+        mu[d0.x + r] = xs;
+        mu[d0.y + r] = xs;
+        mu[d0.z + r] = xs;
+        mu[d0.w + r] = xs;
+        mu[d1.x + r] = xs;
+        mu[d1.y + r] = xs;
+        mu[d1.z + r] = xs;
+        mu[d1.w + r] = xs;
+      }
+      for (; k + 4 <= dg; k += 4) {
+        const int4 dd = *reinterpret_cast<const int4*>(diag + k);
+        mu[dd.x + r] = xs;
+        mu[dd.y + r] = xs;
+        mu[dd.z + r] = xs;
+        mu[dd.w + r] = xs;
+      }
+      for (; k < dg; ++k) mu[diag[k] + r] = xs;
+      if (argk < dg) mu[diag[argk] + r] = y | sg;
+    }
+  }
+}
+
 // One masked BP run (Algorithm 2).  The caller has placed `npairs` packed
 // pairs in LDS and synchronised.  Warm start from `parent` (LDS order) or
 // `parent_csc` (CSC order), else from the priors.  When `cancel` is given the
@@ -403,7 +459,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
                                          uint32_t* err, const FirstIter* fi = nullptr,
                                          bool have_pf = false, uint32_t pf = 0u,
                                          const float* asched = nullptr, int nsched = 0,
-                                         EarlyLoads* early = nullptr) {
+                                         EarlyLoads* early = nullptr, bool d1_done = false) {
   const int tid = fresh_tid(), B = blockDim.x, lane = tid & 63, wave = tid >> 6;
   float* msg = L.msg();
   const bool table = fi && fi->enabled && !parent && !parent_csc && npairs == 0 && T >= 1;
@@ -424,7 +480,7 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     rt[q] = make_uint4(0u, 0u, 0u, 0u);
-    if (table && (R.row[q] >> 31)) rt[q] = fi->rows[q * B + tid];
+    if (table && !d1_done && (R.row[q] >> 31)) rt[q] = fi->rows[q * B + tid];
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -446,54 +502,8 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
       }
     }
   }
-  if (table) {
-    // D(1) on the edges of this thread's rows: magnitude y on the edge of the
-    // least |Lambda|, x elsewhere; sign (-1)^{s_i} times the parity of the
-    // other edges' priors.
-    const int32_t* diag = L.i32(kOffDiag);
-    uint32_t* mu = L.msgu();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int r = q * B + tid;
-      const int dg = (int)((R.row[q] >> 16) & 0xFFu);
-      const uint32_t x = rt[q].x, y = rt[q].y, info = rt[q].z;
-      const int argk = (int)(info & 0xFFu);
-      const uint32_t sg = (((info >> 8) & 1u) ^ sbit[q]) << 31;
-      if ((info >> 9) & 1u) {  // some prior of the row is negative
-        for (int k = 0; k < dg; ++k) {
-          const int pq = diag[k] + r;
-          const uint32_t nb = ((fi->negbits[pq >> 5] >> (pq & 31)) & 1u) << 31;
-          mu[pq] = (k == argk ? y : x) | (sg ^ nb);
-        }
-      } else {
-        // Every edge gets x, then the edge of the least |Lambda| gets y: a
-        // lane's LDS writes land in program order.
-        const uint32_t xs = x | sg;
-        int k = 0;
-        for (; k + 8 <= dg; k += 8) {
-          const int4 d0 = *reinterpret_cast<const int4*>(diag + k);
-          const int4 d1 = *reinterpret_cast<const int4*>(diag + k + 4);
-          mu[d0.x + r] = xs;
-          mu[d0.y + r] = xs;
-          mu[d0.z + r] = xs;
-          mu[d0.w + r] = xs;
-          mu[d1.x + r] = xs;
-          mu[d1.y + r] = xs;
-          mu[d1.z + r] = xs;
-          mu[d1.w + r] = xs;
-        }
-        for (; k + 4 <= dg; k += 4) {
-          const int4 dd = *reinterpret_cast<const int4*>(diag + k);
-          mu[dd.x + r] = xs;
-          mu[dd.y + r] = xs;
-          mu[dd.z + r] = xs;
-          mu[dd.w + r] = xs;
-        }
-        for (; k < dg; ++k) mu[diag[k] + r] = xs;
-        if (argk < dg) mu[diag[argk] + r] = y | sg;
-      }
-    }
-  } else if (parent) {
+  if (table && !d1_done) write_d1<CPT, PW>(g, L, R, fi, rt, sbit);
+  if (parent) {
     const float4* src = reinterpret_cast<const float4*>(parent);
     float4* dst = reinterpret_cast<float4*>(msg);
     for (int i = tid; i < g.nnz_pad / 4; i += B) dst[i] = src[i];
@@ -571,6 +581,11 @@ __device__ __forceinline__ RunRes bp_run(const DevGraph& g, const Lds& L, Res<CP
       L.misc()[0] = cx;
     }
     lds_barrier();
+    if (early && early->fi) {  // loaded here, not across the variable phase: fewer live registers
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (R.row[q] >> 31) early->rt[q] = early->fi->rows[q * B + tid];
+    }
     uint32_t any = 0;
     for (int w = 0; w < g.words_m; w += 2) {
       const uint2 x = *reinterpret_cast<const uint2*>(resid + w);
@@ -1035,7 +1050,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
                                              Res<CPT, PW>& R, long long shot, int ctx,
                                              unsigned long long& nruns, unsigned long long& niters,
                                              int& work_hint, long long next_shot, long long& pf_shot,
-                                             uint32_t& pf, long long& flips_row) {
+                                             uint32_t& pf, long long& flips_row, long long& d1_shot) {
   const DevGraph& g = a.g;
   // The clock is read only when latencies are asked for, by one wave: the
   // read returns on the same counter as LDS operations.
@@ -1048,9 +1063,17 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
   el.lmask = g.lmask;
   el.work_hint = -1;
   el.lm = 0ull;
+  // Batched calls write the next shot's D(1) right after this shot's output,
+  // while other waves finish theirs and thread 0 schedules (see below).
+  const bool spec = !a.stream && next_shot >= 0 && a.fi.enabled && a.init_iters >= 1;
+  el.fi = spec ? &a.fi : nullptr;
+  el.rt[0] = el.rt[1] = make_uint4(0u, 0u, 0u, 0u);
+  const bool d1_done = d1_shot == shot;
+  d1_shot = -1;
   const RunRes rr = bp_run<CPT, PW>(g, L, R, nullptr, nullptr, 0, a.syn + row * g.m,
                                     a.init_iters, true, a.alpha, nullptr, 0, rg, &a.st->error,
-                                    &a.fi, pf_shot == shot, pf, a.alpha_sched, a.n_sched, &el);
+                                    &a.fi, pf_shot == shot, pf, a.alpha_sched, a.n_sched, &el,
+                                    d1_done);
   pf_shot = -1;
   nruns += 1;
   niters += rr.iters;
@@ -1061,6 +1084,16 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, el,
                             next_shot, pf_shot, pf, work_hint, !a.stream);
     if (!a.stream) flips_row = row;  // written after the next scheduling barrier
+    if (spec && rr.iters >= 1) {
+      // The messages of this run are no longer read (the other waves only
+      // read the residual and their registers from here on), so the next
+      // shot's iteration-1 messages can go in now.
+      uint32_t sb[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) sb[q] = (pf >> (8 * q)) & 1u;
+      write_d1<CPT, PW>(g, L, R, &a.fi, el.rt, sb);
+      d1_shot = next_shot;
+    }
     if (threadIdx.x == 0) {
       a.conv[row] = (uint8_t)rr.conv;
       if (a.lat) a.lat[row] = dev_clock() - t0;
@@ -1206,6 +1239,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   long long pf_shot = -1;         // shot whose syndrome bits `pf` holds (uniform)
   uint32_t pf = 0;
   long long flips_row = -1;       // output row whose flips wait in the second accumulator
+  long long d1_shot = -1;         // shot whose iteration-1 messages are already in LDS
   int32_t* misc = L.misc();
   for (int it = 0;; ++it) {
     opaque_res<CPT, PW>(R);
@@ -1328,10 +1362,11 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       flip_write_late(a.g, L, a.flips + flips_row * a.g.k);
       flips_row = -1;
     }
+    if (kind != 2) d1_shot = -1;
     if (kind == 3) break;
     if (kind == 2) {
       if (process_init<CPT, PW>(a, L, R, shot, (int)item, nruns, niters, work_hint, next_shot,
-                                pf_shot, pf, flips_row) &&
+                                pf_shot, pf, flips_row, d1_shot) &&
           tid == 0)
         spare = -1;
     } else if (kind == 1) {
