@@ -1084,6 +1084,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     emit_from_regs<CPT, PW>(g, L, rg.ebits, a.corr + row * g.n, a.flips + row * g.k, el,
                             next_shot, pf_shot, pf, work_hint, !a.stream);
     if (!a.stream) flips_row = row;  // written after the next scheduling barrier
+    const uint32_t lat = (a.lat && threadIdx.x == 0) ? dev_clock() - t0 : 0u;
     if (spec && rr.iters >= 1) {
       // The messages of this run are no longer read (the other waves only
       // read the residual and their registers from here on), so the next
@@ -1096,7 +1097,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     }
     if (threadIdx.x == 0) {
       a.conv[row] = (uint8_t)rr.conv;
-      if (a.lat) a.lat[row] = dev_clock() - t0;
+      if (a.lat) a.lat[row] = lat;
       __hip_atomic_fetch_add(&a.st->done, 1ull, __ATOMIC_RELAXED, AGENT);
     }
     publish_done(a, shot);
