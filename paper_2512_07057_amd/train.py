@@ -53,6 +53,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=0.01)
     ap.add_argument("--eval-shots", type=int, default=100_000)
     ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--train", choices=["both", "alpha", "lambda"], default="both",
+                    help="which factors to learn (the others keep their defaults)")
     args = ap.parse_args(argv)
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -66,7 +68,10 @@ def main(argv=None):
     lam0 = np.log((1 - pr.p) / pr.p)
     lam = torch.tensor(lam0, dtype=torch.float32, device="cuda", requires_grad=True)
     alpha = torch.full((args.T,), 0.625, dtype=torch.float32, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([lam, alpha], lr=args.lr)
+    learn = {"both": [lam, alpha], "alpha": [alpha], "lambda": [lam]}[args.train]
+    for t in (lam, alpha):
+        t.requires_grad_(any(t is x for x in learn))
+    opt = torch.optim.Adam(learn, lr=args.lr)
     losses = []
     t0 = time.perf_counter()
     for step in range(args.steps):
@@ -105,7 +110,8 @@ def main(argv=None):
     lrn = ler(learned, bsd.FLAG_ALPHA_SCHEDULE)
     n = args.eval_shots
     res = {
-        "problem": args.problem, "T": args.T, "K": args.K, "batch": args.batch, "steps": args.steps,
+        "problem": args.problem, "train": args.train, "T": args.T, "K": args.K, "batch": args.batch,
+        "steps": args.steps,
         "lr": args.lr, "train_seconds": train_s, "loss_first": losses[0], "loss_last": losses[-1],
         "alpha_learned": [round(float(a), 4) for a in alpha.detach().cpu().numpy()],
         "lambda_change_rms": float(np.sqrt(np.mean((lam_l - lam0) ** 2))),
