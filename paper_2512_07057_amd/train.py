@@ -10,7 +10,8 @@ the library's kernels (bsd_unroll_*), checkpoints every K iterations.
 Evaluation: the beam-search decoder at beam width 8 (100 iterations: 20
 initial + 10 rounds x 8) on held-out shots, once with the defaults (alpha =
 0.625, the true priors) and once with the learned factors (the schedule
-alpha_t for iteration t of every run, the priors p_j = 1 / (1 + e^Lambda_j)).
+alpha_t for iteration t of every run, the priors p_j = 1 / (1 + e^Lambda_j)),
+and the same two with BP alone (the initial run of 20 iterations, no beam).
 Prints one JSON line.
 
     python -m paper_2512_07057_amd.train --steps 300
@@ -95,9 +96,9 @@ def main(argv=None):
     syn = torch.from_numpy(ev["syndromes"]).cuda()
     P = workloads.params_100iters(8)
 
-    def ler(c, flags):
-        prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round, 1,
-                              P.alpha, bsd.MODE_BATCHED, flags)
+    def ler(c, flags, rounds=None):
+        prm = bsd.make_params(P.max_rounds if rounds is None else rounds, P.beam_width,
+                              P.initial_iters, P.iters_per_round, 1, P.alpha, bsd.MODE_BATCHED, flags)
         out = c.decode(syn, prm)
         fail = (out["converged"].cpu().numpy() == 0) | \
                (out["flips"].cpu().numpy() != ev["true_flips"]).any(1)
@@ -108,6 +109,9 @@ def main(argv=None):
     learned = bsd.Code(pr.m, pr.n, pr.colptr, pr.rowidx, 1.0 / (1.0 + np.exp(lam_l)), pr.L)
     learned.set_alpha_schedule(alpha.detach().cpu().numpy())
     lrn = ler(learned, bsd.FLAG_ALPHA_SCHEDULE)
+    # The same factors in plain BP (the initial run only, no beam).
+    base_bp = ler(code, 0, rounds=0)
+    lrn_bp = ler(learned, bsd.FLAG_ALPHA_SCHEDULE, rounds=0)
     n = args.eval_shots
     res = {
         "problem": args.problem, "train": args.train, "T": args.T, "K": args.K, "batch": args.batch,
@@ -118,6 +122,8 @@ def main(argv=None):
         "eval_shots": n, "decoder": "beam 8, 20 + 10 x 8 iterations",
         "ler_default": base / n, "ler_default_interval": wilson(base, n),
         "ler_learned": lrn / n, "ler_learned_interval": wilson(lrn, n),
+        "bp_only_iters": P.initial_iters,
+        "ler_bp_only_default": base_bp / n, "ler_bp_only_learned": lrn_bp / n,
     }
     print(json.dumps(res), flush=True)
 
