@@ -141,7 +141,9 @@ struct RunRes {
 // step after it, so that they complete while the run computes instead of on
 // the way out: the next shot's syndrome bits (after the prologue), the
 // logical mask of each lane's lowest set hard decision and the work queue's
-// length (after each variable phase).  Values are consumed only on output.
+// length (after each variable phase), and the first-iteration table entries
+// for the next shot (after each convergence barrier).  Values are consumed
+// only on output.
 struct EarlyLoads {
   const uint8_t* next_syn;          // next shot's syndrome, or nullptr
   const int32_t* work_count;        // read by thread 0
