@@ -197,9 +197,9 @@ bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, in
  *
  * A server keeps one persistent decoder per code running on the GPU, each on
  * its own stream with its own workgroups.  By default a code whose BP run
- * fills a compute unit's LDS gets one workgroup on each of 1/16 of the units,
- * and any other code 2 x beam_width workgroups (at least 32): sizes for a
- * few thousand requests per second per code, since idle workgroups poll.
+ * fills a compute unit's LDS gets one workgroup on each of 1/32 of the units,
+ * and any other code beam_width workgroups (at least 16): sizes for a few
+ * thousand requests per second per code, since idle workgroups poll.
  * Heavier loads pass larger grid_blocks.  Requests pass through a ring per
  * code in pinned host memory.  The host writes the syndrome and publishes it,
  * and the decoder claims it as soon as one of its workgroups is free.  This

@@ -1238,9 +1238,9 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
   // Automatic sizes.  Idle workgroups poll the queue counters, and on a
   // mixed load of a few thousand requests per second per code fewer
   // workgroups gave lower latency at every percentile: a code whose run
-  // fills a compute unit's LDS gets ncu/16 workgroups (one per unit), any
-  // other code as many as the children of one round of a deep shot
-  // (2 x beam width, at least 32), so that round runs side by side.
+  // fills a compute unit's LDS gets ncu/32 workgroups (one per unit), any
+  // other code one per beam path (at least 16), half the children of one
+  // round of a deep shot.
   const int64_t budget = ring_bytes > 0 ? ring_bytes : (int64_t)64 << 20;
   for (int i = 0; i < ncodes; ++i) {
     ServeQ& q = s->q[i];
@@ -1251,8 +1251,8 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
     q.prm = params[i];
     const bool big = c->lds > 64 * 1024;
     q.grid = grid_blocks && grid_blocks[i] > 0 ? grid_blocks[i]
-             : big ? std::max(1, ncu / 16)
-                   : std::min(c->grid, std::max(32, 2 * q.prm.beam_width));
+             : big ? std::max(1, ncu / 32)
+                   : std::min(c->grid, std::max(16, q.prm.beam_width));
     const DevGraph& g = c->g;
     const size_t per = (size_t)g.m + g.n + std::max(g.k, 1) + 1 + 8;
     uint64_t rows = 64;
