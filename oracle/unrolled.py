@@ -119,8 +119,9 @@ def loss_and_grads(g: Graph, lam0, alpha0, syn, err, grad_post=None):
     else:
         obj = bce_loss(post, err)
     obj.backward()
-    return (float(obj.detach()), post.detach().numpy(), lam.grad.numpy().copy(),
-            alpha.grad.numpy().copy())
+    # a parameter the output does not depend on (alpha when T = 0) has no .grad
+    grad = lambda x: np.zeros(x.shape) if x.grad is None else x.grad.numpy().copy()
+    return float(obj.detach()), post.detach().numpy(), grad(lam), grad(alpha)
 
 
 def min_tie_gap(g: Graph, lam0, alpha0, syn):

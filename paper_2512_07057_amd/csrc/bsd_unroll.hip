@@ -148,7 +148,9 @@ __global__ void k_unroll_bwd(UnrollArgs a) {
   const F lim = (F)a.llr_max;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int e = threadIdx.x; e < nnz; e += blockDim.x) gE[e] = F(0);  // E(T) does not reach the loss
-  for (int j = threadIdx.x; j < a.n; j += blockDim.x) gL[j] = F(0);
+  // With no iteration post(0) = Lambda, so dL/dLambda starts at dL/dpost;
+  // otherwise post(T) reaches Lambda through the variable phase of t = T.
+  for (int j = threadIdx.x; j < a.n; j += blockDim.x) gL[j] = a.T == 0 ? gpost[j] : F(0);
   __syncthreads();
   for (int seg = a.nseg - 1; seg >= 0; --seg) {
     const int t0 = seg * a.K, t1 = min(t0 + a.K, a.T);

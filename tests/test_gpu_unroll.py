@@ -176,3 +176,18 @@ def test_decoder_alpha_schedule_bitexact_vs_oracle(bsd, oracle_mod, mode):
         bad = np.nonzero((got != ref[k]).reshape(shots, -1).any(1))[0]
         assert bad.size == 0, f"{k} differ on shots {bad[:10]}"
     gc.log("schedule mode", mode, "deep", out["stats"]["deep_shots"])
+
+
+def test_zero_iterations_gradient_is_grad_post(bsd, setup):
+    """With T = 0 the output is post(0) = Lambda, so dL/dLambda is dL/dpost
+    summed over shots (the oracle's autograd of the same definition)."""
+    from oracle import unrolled as U
+    pr, code, syn, err, lam, alpha = setup
+    g = U.Graph.from_problem(pr)
+    s, e = syn[:8], err[:8]
+    loss_o, post_o, gl_o, ga_o = U.loss_and_grads(g, lam, alpha[:0], s, e)
+    loss, post, gl, ga = _gpu(bsd, code, lam, alpha[:0], s, e, torch.float64)
+    assert ga.shape == (0,) and ga_o.shape == (0,)
+    np.testing.assert_array_equal(post, np.broadcast_to(lam, post.shape))
+    assert _rel(gl, gl_o) <= 1e-12
+    assert np.abs(gl).max() > 0
