@@ -84,7 +84,14 @@ typedef enum {
   /* Scale eq. (1) at iteration t of every BP run (initial and masked) by the
    * code's schedule entry min(t, n) (bsd_code_set_alpha_schedule) instead of
    * alpha: the per-iteration factors the unrolled decoder learns. */
-  BSD_FLAG_ALPHA_SCHEDULE = 4
+  BSD_FLAG_ALPHA_SCHEDULE = 4,
+  /* Batched mode: skip the sparse screen of iteration 1.  By default, when
+   * every prior LLR is positive, initial_iters >= 1 and num_results = 1, a
+   * first kernel computes iteration 1 of each shot's initial run only for
+   * the columns of its flipped detectors (every other column decides 0 at
+   * t = 1) and finishes the shots that converge there; the persistent
+   * decoder takes the rest.  Results are identical either way. */
+  BSD_FLAG_NO_SCREEN = 8
 } bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */

@@ -22,6 +22,7 @@ MODE_BATCHED, MODE_PLAIN = 0, 1
 FLAG_GRAPH = 1
 FLAG_DENSE_FIRST = 2
 FLAG_ALPHA_SCHEDULE = 4
+FLAG_NO_SCREEN = 8
 _lib = None
 
 

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsd.so")
 SOURCES = ["bsd_kernels_common.hip", "bsd_kernels_pw1.hip", "bsd_kernels_pw2.hip",
-           "bsd_kernels_pw3.hip", "bsd_kernels_pw4.hip", "bsd_unroll.hip", "bsd_host.hip"]
+           "bsd_kernels_pw3.hip", "bsd_kernels_pw4.hip", "bsd_unroll.hip", "bsd_screen.hip",
+           "bsd_host.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -31,16 +32,25 @@ def hipcc() -> str:
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every source to an object in parallel, then link libbsd.so."""
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source to an object in parallel, then link libbsd.so.
+    With `incremental`, an object newer than its source and every header is
+    kept."""
     from concurrent.futures import ThreadPoolExecutor
 
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
 
+    headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    headers.append(os.path.join(os.path.dirname(HERE), "include", "bsd.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
+
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > max(
+                newest_header, os.path.getmtime(os.path.join(CSRC, src))):
+            return obj
         cmd = [hipcc(), *compile_flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)

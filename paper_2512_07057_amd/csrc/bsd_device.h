@@ -850,6 +850,12 @@ __device__ __forceinline__ char* slot_ptr(const BatchArgs& a, int ctx, int s) {
 
 __device__ __forceinline__ uint32_t dev_clock() { return (uint32_t)wall_clock64(); }
 
+// A shot's latency: with the iteration-1 screen in front, its share was
+// written first and this kernel's time is added (one thread).
+__device__ __forceinline__ void put_latency(const BatchArgs& a, long long row, uint32_t ticks) {
+  a.lat[row] = a.shot_list ? a.lat[row] + ticks : ticks;
+}
+
 // Row of a shot's syndrome and outputs (serving: a ring slot).
 __device__ __forceinline__ long long io_row(const BatchArgs& a, long long shot) {
   return a.stream ? (long long)((unsigned long long)shot & a.io_mask) : shot;
@@ -875,7 +881,7 @@ __device__ __forceinline__ void finish_deep(const BatchArgs& a, const Lds& L, in
   emit_from_bits(g, L, bits, a.corr + row * g.n, a.flips + row * g.k);
   if (threadIdx.x == 0) {
     a.conv[row] = (uint8_t)converged;
-    if (a.lat) a.lat[row] = dev_clock() - t_start;
+    if (a.lat) put_latency(a, row, dev_clock() - t_start);
   }
   publish_done(a, shot);
   // The barrier orders every lane's writes before thread 0's release in
@@ -1099,7 +1105,7 @@ __device__ __forceinline__ bool process_init(const BatchArgs& a, const Lds& L,
     }
     if (threadIdx.x == 0) {
       a.conv[row] = (uint8_t)rr.conv;
-      if (a.lat) a.lat[row] = lat;
+      if (a.lat) put_latency(a, row, lat);
       __hip_atomic_fetch_add(&a.st->done, 1ull, __ATOMIC_RELAXED, AGENT);
     }
     publish_done(a, shot);
@@ -1233,7 +1239,12 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   }
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
-  long long cnext = 0, cend = 0;  // thread 0 only: claimed shots [cnext, cend)
+  long long cnext = 0, cend = 0;  // thread 0 only: claimed positions [cnext, cend)
+  // Thread 0 only: positions to claim, and the shot at a position (the
+  // screen's list, written by the previous kernel, or the identity).
+  long long nclaim = a.shots;
+  if (a.shot_list && tid == 0) nclaim = __hip_atomic_load(&a.st->listed, __ATOMIC_RELAXED, AGENT);
+  auto shot_at = [&](long long q) -> long long { return a.shot_list ? (long long)a.shot_list[q] : q; };
   bool exhausted = false;         // thread 0 only
   int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
   bool idling = false;            // thread 0 only, serving: in an idle stretch since idle_since
@@ -1284,19 +1295,19 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
             const unsigned long long b = __hip_atomic_fetch_add(
                 &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
             cnext = (long long)b;
-            cend = (long long)b + kChunk < a.shots ? (long long)b + kChunk : a.shots;
-            if (cnext >= a.shots) exhausted = true;
+            cend = (long long)b + kChunk < nclaim ? (long long)b + kChunk : nclaim;
+            if (cnext >= nclaim) exhausted = true;
           }
           if (cnext < cend) {
             kind = 2;
-            shot = cnext++;
+            shot = shot_at(cnext++);
             item = (uint32_t)spare;
             if (cnext >= cend && !exhausted) {  // claim the next chunk now: its first shot is prefetched
               const unsigned long long b = __hip_atomic_fetch_add(
                   &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
               cnext = (long long)b;
-              cend = (long long)b + kChunk < a.shots ? (long long)b + kChunk : a.shots;
-              if (cnext >= a.shots) exhausted = true;
+              cend = (long long)b + kChunk < nclaim ? (long long)b + kChunk : nclaim;
+              if (cnext >= nclaim) exhausted = true;
             }
           }
         }
@@ -1351,7 +1362,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       box[1] = (int)item;
       box[2] = (int)(shot & 0xFFFFFFFF);
       box[3] = (int)(shot >> 32);
-      const long long nx = (kind == 2 && cnext < cend) ? cnext : -1;
+      const long long nx = (kind == 2 && cnext < cend) ? shot_at(cnext) : -1;
       box[4] = (int)(nx & 0xFFFFFFFF);
       box[5] = (int)(nx >> 32);
     }

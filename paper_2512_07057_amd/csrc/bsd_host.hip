@@ -89,6 +89,18 @@ struct bsd_code_s {
   bool fi_valid = false;
   uint4* d_rows = nullptr;
   uint32_t* d_negbits = nullptr;
+  // Iteration-1 screen: rows in CSR form, each column's rows, the per-row
+  // table of iteration 1 by original row (with fi), and the list of shots it
+  // hands to the dense decoder (grown on demand).
+  bool all_pos = false;  // every prior LLR > 0 in single precision
+  int32_t* s_rowptr = nullptr;
+  uint4* s_edgerows = nullptr;
+  uint2* s_edgecol = nullptr;
+  int screen_per_cu = 1;
+  int maxdeg_col = 1;
+  uint4* d_rowtab = nullptr;
+  int32_t* d_list = nullptr;
+  int64_t list_cap = 0;
   // Batched workspace of bsd_decode (grown on demand).
   BatchWs ws;
   size_t slot_stride = 0;
@@ -108,6 +120,7 @@ struct bsd_code_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<char> gkey;
   int grid_frac_half = 0;  // autotuner: use half the resident workgroups
+  int ncu = 1;             // compute units of the device
 };
 
 namespace {
@@ -461,7 +474,7 @@ bsd_status ensure_first(bsd_code c, float alpha) {
     for (int e = cp[j]; e < cp[j + 1]; ++e) ecol[e] = j;
   std::vector<std::vector<int>> rows(m);
   for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);  // ascending column = diagonal order
-  std::vector<uint4> rt((size_t)m);
+  std::vector<uint4> rt((size_t)m), rtab((size_t)m, make_uint4(0u, 0u, 0xFFFFFFFFu, 0u));
   std::vector<uint32_t> neg((size_t)g.nnz_pad / 32 + 1, 0u);
   for (int i = 0; i < m; ++i) {
     float m1 = kLlrMax, m2 = kLlrMax;
@@ -487,15 +500,18 @@ bsd_status ensure_first(bsd_code c, float alpha) {
     std::memcpy(&xb, &x, 4);
     std::memcpy(&yb, &y, 4);
     rt[rank] = make_uint4(xb, yb, (uint32_t)argk | ((uint32_t)par << 8) | ((uint32_t)anyneg << 9), 0u);
+    rtab[i] = make_uint4(xb, yb, (uint32_t)ecol[rows[i][argk]], 0u);
   }
   if (!c->d_rows) {
     if (hipMalloc((void**)&c->d_rows, (size_t)m * sizeof(uint4)) != hipSuccess ||
+        hipMalloc((void**)&c->d_rowtab, (size_t)m * sizeof(uint4)) != hipSuccess ||
         hipMalloc((void**)&c->d_negbits, neg.size() * 4) != hipSuccess) {
       (void)hipGetLastError();
       return fail(BSD_ENOMEM, "cannot allocate the first-iteration table");
     }
   }
   HIP_OR_FAIL(hipMemcpy(c->d_rows, rt.data(), (size_t)m * sizeof(uint4), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipMemcpy(c->d_rowtab, rtab.data(), (size_t)m * sizeof(uint4), hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(c->d_negbits, neg.data(), neg.size() * 4, hipMemcpyHostToDevice));
   c->fi.rows = c->d_rows;
   c->fi.negbits = c->d_negbits;
@@ -542,6 +558,49 @@ bsd_status batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, BatchAr
   return BSD_OK;
 }
 
+// Whether a batched call starts with the sparse screen of iteration 1: the
+// initial run from the priors has an iteration 1 whose check phase comes
+// from the table (every prior LLR positive), and a shot that converges there
+// is finished (one result wanted).
+bool use_screen(const bsd_code c, const bsd_params* p, const BatchArgs& a) {
+  return !(p->flags & (BSD_FLAG_DENSE_FIRST | BSD_FLAG_NO_SCREEN)) && p->initial_iters >= 1 &&
+         p->num_results == 1 && c->all_pos && a.fi.enabled;
+}
+
+ScreenArgs screen_args(const bsd_code c, const BatchArgs& a) {
+  const DevGraph& g = c->g;
+  ScreenArgs sa{};
+  sa.m = g.m;
+  sa.n = g.n;
+  sa.k = g.k;
+  sa.words_m = (g.m + 31) / 32;
+  const uintptr_t cp = (uintptr_t)a.corr;
+  sa.vec = (g.n % 16 == 0 && cp % 16 == 0) ? 16 : (g.n % 4 == 0 && cp % 4 == 0) ? 4 : 1;
+  sa.syn8 = (g.m % 8 == 0 && (uintptr_t)a.syn % 8 == 0) ? 1 : 0;
+  sa.maxdeg_col = c->maxdeg_col;
+  sa.row_ptr = c->s_rowptr;
+  sa.edge_rows = c->s_edgerows;
+  sa.edge_col = c->s_edgecol;
+  sa.row_tab = c->d_rowtab;
+  sa.lmask = g.lmask;
+  sa.shots = a.shots;
+  sa.syn = a.syn;
+  sa.corr = a.corr;
+  sa.flips = a.flips;
+  sa.conv = a.conv;
+  sa.lat = a.lat;
+  sa.st = a.st;
+  sa.list = const_cast<int32_t*>(a.shot_list);
+  return sa;
+}
+
+// Screen grid: the workgroups that fit on the device at once (each holds the
+// row tables in LDS), fewer for small batches; each wave strides over shots.
+int screen_grid(const bsd_code c, int64_t shots) {
+  const int64_t want = (shots + kScreenBlock / 64 - 1) / (kScreenBlock / 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)c->screen_per_cu * c->ncu));
+}
+
 bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
                           uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
                           bsd_stats* stats, uint32_t* lat) {
@@ -556,6 +615,23 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.flips = flips;
   a.conv = conv;
   a.lat = lat;
+  const bool screen = use_screen(c, p, a);
+  if (screen) {
+    if (c->list_cap < shots) {
+      hipFree(c->d_list);
+      c->d_list = nullptr;
+      c->list_cap = 0;
+      if (hipMalloc((void**)&c->d_list, (size_t)shots * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BSD_ENOMEM, "cannot allocate the screen's shot list (%lld shots)", (long long)shots);
+      }
+      c->list_cap = shots;
+      drop_graph(c);
+    }
+    a.shot_list = c->d_list;
+  }
+  const ScreenArgs sa = screen_args(c, a);
+  const int sgrid = screen_grid(c, shots);
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
     std::vector<char> key(sizeof a + 3 * sizeof(int));
@@ -567,6 +643,7 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
       if (!c->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       HIP_OR_FAIL(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e1 = launch_batch_reset(a, c->cap_stream);
+      if (e1 == hipSuccess && screen) e1 = launch_screen(sa, sgrid, c->cap_stream);
       hipError_t e2 = launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, c->cap_stream);
       hipGraph_t gr = nullptr;
       hipError_t e3 = hipStreamEndCapture(c->cap_stream, &gr);
@@ -584,6 +661,7 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   } else {
     HIP_OR_FAIL(launch_batch_reset(a, s));
     HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+    if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, s));
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
     HIP_OR_FAIL(hipEventRecord(c->ev1, s));
   }
@@ -620,6 +698,7 @@ bsd_status set_geometry(bsd_code c, int block, int half) {
     return fail(BSD_EDEVICE, "occupancy query failed: %s (blocks per CU %d)", hipGetErrorString(he), per_cu);
   const int grid = half && per_cu > 1 ? (per_cu / 2) * ncu : per_cu * ncu;
   if (grid != c->grid || block != c->block) drop_graph(c);
+  c->ncu = ncu;
   c->block = block;
   c->cpt = cpt;
   c->grid = grid;
@@ -754,7 +833,43 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     delete c;
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
+  // Screen of iteration 1: rows in CSR form (ascending columns); per edge in
+  // that order, its column's rows (original numbering, ascending) and its
+  // column with the column's prior LLR.
+  std::vector<int32_t> srp(m + 1, 0);
+  std::vector<uint16_t> ser((size_t)nnz * 8, 0xFFFFu);
+  std::vector<uint32_t> sec((size_t)nnz * 2);
+  for (int e = 0; e < nnz; ++e) srp[h_rowidx[e] + 1]++;
+  for (int i = 0; i < m; ++i) srp[i + 1] += srp[i];
+  {
+    std::vector<int32_t> fill(srp.begin(), srp.end() - 1);
+    for (int j = 0; j < n; ++j)
+      for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+        const int q = fill[h_rowidx[e]]++;
+        for (int f = h_colptr[j]; f < h_colptr[j + 1]; ++f)
+          ser[(size_t)q * 8 + (f - h_colptr[j])] = (uint16_t)h_rowidx[f];
+        uint32_t lb;
+        std::memcpy(&lb, &lam[j], 4);
+        sec[(size_t)q * 2] = (uint32_t)j;
+        sec[(size_t)q * 2 + 1] = lb;
+      }
+  }
   c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_cr, d_lam, d_lm, d_l64};
+  c->all_pos = true;
+  for (int j = 0; j < n; ++j) c->all_pos = c->all_pos && lam[j] > 0.f;
+  uint16_t* d_ser = nullptr;
+  uint32_t* d_sec = nullptr;
+  if (dev_upload(&c->s_rowptr, srp) != hipSuccess || dev_upload(&d_ser, ser) != hipSuccess ||
+      dev_upload(&d_sec, sec) != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(d_ser);
+    hipFree(d_sec);
+    bsd_code_destroy(c);
+    return fail(BSD_ENOMEM, "cannot upload the graph");
+  }
+  c->s_edgerows = reinterpret_cast<uint4*>(d_ser);
+  c->s_edgecol = reinterpret_cast<uint2*>(d_sec);
+  c->screen_per_cu = screen_blocks_per_cu(m);
   c->d_lam64 = d_l64;
   g.diag_ptr = d_diag;
   g.row_of_rank = d_ror;
@@ -776,6 +891,7 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   int maxdeg_col = 1;
   for (int j = 0; j < n; ++j) maxdeg_col = std::max(maxdeg_col, h_colptr[j + 1] - h_colptr[j]);
   c->pw = (maxdeg_col + 1) / 2;
+  c->maxdeg_col = maxdeg_col;
   // A workgroup of 1024 lanes holds up to 9 columns per lane in registers;
   // beyond that 512 lanes get twice the registers.  Small graphs get 512-lane
   // workgroups, two per CU: with thousands of single-wave workgroups, the
@@ -822,6 +938,11 @@ bsd_status bsd_code_destroy(bsd_code c) {
   hipFree(c->u_rowptr);
   hipFree(c->u_rowedge);
   hipFree(c->d_negbits);
+  hipFree(c->d_rowtab);
+  hipFree(c->s_rowptr);
+  hipFree(c->s_edgerows);
+  hipFree(c->s_edgecol);
+  hipFree(c->d_list);
   ws_free(c->ws);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);

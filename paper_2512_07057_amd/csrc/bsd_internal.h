@@ -100,6 +100,8 @@ struct BatchState {
   unsigned long long pub;  // shots published
   uint32_t stop;           // nonzero: end the kernel
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
+  int32_t listed;          // shots the iteration-1 screen handed to the dense decoder
+  int32_t pad0;
 };
 
 // The check phase of iteration 1 in a run from the priors with no masked
@@ -157,6 +159,11 @@ struct BatchArgs {
   const float* alpha_sched;  // or NULL: iteration t scales eq. (1) by alpha_sched[min(t, n_sched) - 1]
   int32_t n_sched;
   BatchState* st;
+  // With the iteration-1 screen: the shots left to this kernel, in claim
+  // order (st->listed of them); without it every shot 0..shots-1.  The
+  // screen has already written the outputs of the others and counted them
+  // as done, and its share of each listed shot's latency.
+  const int32_t* shot_list;
   uint32_t* work_ring;
   uint32_t work_cap;      // power of two
   uint32_t* ctx_ring;
@@ -167,6 +174,44 @@ struct BatchArgs {
   size_t slot_stride;
   int32_t slots_per_ctx;  // 3 * bw + 1 (the last one keeps the initial run's hard decision)
 };
+
+// Sparse check of iteration 1 of the initial run, one wavefront per shot.
+// From E(0) = Lambda with every Lambda_j > 0, eq. (1) at t = 1 sends each
+// column a message of magnitude x_i (the row's least alpha |Lambda|) or y_i
+// (the second least, to the edge holding the least) with the sign
+// (-1)^{s_i}.  A column with no flipped detector therefore has a positive
+// posterior and decides 0, so the hard decision of iteration 1 is found by
+// summing the posteriors of the columns of flipped detectors only, in the
+// same single-precision order as the dense variable phase.  Shots whose
+// decision satisfies the syndrome are finished here (one iteration, one
+// run); the others are appended to `list` for the dense decoder.
+struct ScreenArgs {
+  int32_t m, n, k;
+  int32_t words_m;
+  int32_t vec;                 // bytes per correction store: 16, 4 or 1 (divides n; aligned)
+  int32_t syn8;                // 1: m % 8 == 0 and the syndromes are 8-byte aligned
+  int32_t maxdeg_col;          // largest column degree (1..8)
+  const int32_t* row_ptr;      // [m + 1] rows (original numbering) in CSR form
+  const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
+                               //   ascending (0xFFFF unused)
+  const uint2* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits
+  const uint4* row_tab;        // [m] x bits, y bits, column of the least |Lambda|, 0
+  const uint64_t* lmask;       // [n]
+  long long shots;
+  const uint8_t* syn;
+  uint8_t* corr;
+  uint8_t* flips;
+  uint8_t* conv;
+  uint32_t* lat;               // or NULL
+  BatchState* st;              // error, done, runs, iterations, listed
+  int32_t* list;               // [shots]
+};
+constexpr int kScreenBlock = 512;        // eight shots in flight per workgroup
+constexpr int kScreenMaxFlipped = 64;    // more flipped detectors: dense decoder
+constexpr int kScreenMaxCand = 1024;     // more (detector, column) pairs: dense decoder
+constexpr int kScreenMaxSet = 64;        // more set decisions: dense decoder
+size_t screen_lds_bytes(int m);
+int screen_blocks_per_cu(int m);
 
 // Arguments of a single BP run launched on its own (plain form, bsd_bp_run).
 struct SingleArgs {
@@ -212,6 +257,7 @@ hipError_t launch_single(const SingleArgs& a, int block, int cpt, int pw, size_t
 hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, int pw, size_t lds,
                           hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+hipError_t launch_screen(const ScreenArgs& a, int grid, hipStream_t s);
 
 constexpr int kMaxServe = 8;  // codes one server can hold
 

@@ -29,6 +29,7 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->pub = 0;
     a.st->stop = 0;
     a.st->poll_token = 0;
+    a.st->listed = 0;
   }
 }
 
