@@ -8,11 +8,14 @@ beam32_340iters (max_rounds 10, beam_width 32, initial_iters 40,
 iters_per_round 30) with scaling 0.625 and fp32 messages.
 
 A step decodes the whole batch (syndromes already in device memory) with
-one call of the batched persistent decoder.  Printed as one JSON line:
-shots/s, per-shot device decode latency percentiles, the plain
+one call of the batched decoder: the iteration-1 screen, then the
+persistent decoder for the shots the screen hands on.  Printed as one JSON
+line: shots/s, per-shot device decode latency percentiles, the plain
 one-launch-per-BP-run form's shots/s on a prefix of the same syndromes, the
-roofline position of the decoding kernel and the CPU oracle's rate on a
-bounded sample.
+call's position against the HBM floor of its mandatory input and output,
+legs for beams of uneven depth (faults drawn at 40x the priors) and for the
+[[144,12,12]] code-capacity workload, the serving loop, and the CPU oracle's
+rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -30,7 +34,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shots/sec + p99.9 decode latency, BB144 12-round, beam 32; batched vs plain"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bsd_batched_w2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_w2_decode.json")
+LEGS = ("host", "plain", "hot", "w1", "serving", "cpu")
 
 
 def kernel_source_digest() -> str:
@@ -44,8 +49,8 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(units_bytes_per_launch):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+def measured_traffic():
+    """HBM bytes per call from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -54,34 +59,61 @@ def measured_traffic(units_bytes_per_launch):
         return None
     if t.get("kernel_source_digest") != kernel_source_digest():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
 
 
-def cpu_baseline(pr, params, syn_all, target_s=10.0):
+def pct(x, q):
+    return float(np.percentile(x, q)) if len(x) else None
+
+
+def host_cpu():
+    info = {"threads": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Core(s) per socket", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(pr, params, syn_all, target_s=8.0):
+    """The oracle on the host cores: single precision in the GPU's operation
+    order (the value) and double precision, both built -O3 -march=native
+    without FMA contraction; one shot per thread over every host thread."""
     import oracle
-    op = oracle.OracleProblem.from_problem(pr)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    probe = min(2000, len(syn_all))
-    t0 = time.perf_counter()
-    op.decode_params(syn_all[:probe], params, dtype=np.float64, threads=cores)
-    dt = time.perf_counter() - t0
-    n = int(min(len(syn_all), max(probe, probe * target_s / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    op.decode_params(syn_all[:n], params, dtype=np.float64, threads=cores)
-    dt = time.perf_counter() - t0
+    op = oracle.OracleProblem.from_problem(pr, flavour="native")
+    res = {}
+    for name, dt in (("f32", np.float32), ("f64", np.float64)):
+        probe = min(2000, len(syn_all))
+        t0 = time.perf_counter()
+        op.decode_params(syn_all[:probe], params, dtype=dt, threads=cores)
+        dt_probe = time.perf_counter() - t0
+        n = int(min(len(syn_all), max(probe, probe * target_s / max(dt_probe, 1e-6))))
+        t0 = time.perf_counter()
+        op.decode_params(syn_all[:n], params, dtype=dt, threads=cores)
+        wall = time.perf_counter() - t0
+        res[name] = {"shots_per_s": n / wall, "shots": n, "wall_s": wall}
     # single-thread time per shot (the kind of figure the paper reports for its CPU decoder)
     nl = min(1000, len(syn_all))
     per = np.empty(nl)
     for i in range(nl):
         t1 = time.perf_counter()
-        op.decode_params(syn_all[i:i + 1], params, dtype=np.float64, threads=1)
+        op.decode_params(syn_all[i:i + 1], params, dtype=np.float32, threads=1)
         per[i] = (time.perf_counter() - t1) * 1e6
-    return {"value": n / dt, "unit": "shots/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} of the benchmark's syndromes, double-precision oracle, "
-                      f"one shot per thread over {cores} host threads, {dt:.1f} s wall",
-            "single_thread_latency_us": {"p50": float(np.percentile(per, 50)),
-                                         "p99": float(np.percentile(per, 99)),
-                                         "p999": float(np.percentile(per, 99.9)), "shots": nl}}
+    f32 = res["f32"]
+    return {"value": f32["shots_per_s"], "unit": "shots/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {f32['shots']} of the benchmark's syndromes, single-precision "
+                      f"oracle in the GPU's operation order (-O3 -march=native, no FMA "
+                      f"contraction), one shot per thread over {cores} host threads, "
+                      f"{f32['wall_s']:.1f} s wall",
+            "f64": res["f64"], "host": host_cpu(),
+            "single_thread_latency_us": {"p50": pct(per, 50), "p99": pct(per, 99),
+                                         "p999": pct(per, 99.9), "shots": nl}}
 
 
 def serving(bsd, torch, w2_code, w2_syn, w2_corr, seconds=2.0, rate=20_000.0):
@@ -128,6 +160,80 @@ def serving(bsd, torch, w2_code, w2_syn, w2_corr, seconds=2.0, rate=20_000.0):
                     "result on the host clock"}
 
 
+def timed_calls(code, syn, prm, steps, torch):
+    """`steps` decode calls after one warm-up; per-call stats and wall time."""
+    code.decode(syn, prm)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(code.decode(syn, prm)["stats"])
+    torch.cuda.synchronize()
+    return stats, time.perf_counter() - t0
+
+
+def hot_leg(bsd, torch, code, pr, P, shots=2000, mult=40.0, steps=3):
+    """Beams of uneven depth on the headline graph: faults drawn at `mult` x
+    the priors (the decoder keeps the true priors), so most shots enter
+    beam rounds.  Work rate and the slot traffic of the child runs: each
+    child reads its parent's messages and writes its own (nnz_pad fp32 each)."""
+    from bsd_inputs import sampler
+    hot = type("Hot", (), {"p": np.minimum(pr.p * mult, 0.4), "colptr": pr.colptr,
+                           "rowidx": pr.rowidx, "m": pr.m, "k": pr.k, "L": pr.L})()
+    d = sampler.sample(hot, shots, 0)
+    syn = torch.from_numpy(np.ascontiguousarray(d["syndromes"])).cuda()
+    prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                          P.num_results, P.alpha, bsd.MODE_BATCHED)
+    stats, wall = timed_calls(code, syn, prm, steps, torch)
+    r = code.decode(syn, prm, latency=True)
+    torch.cuda.synchronize()
+    lat = r["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0
+    conv = r["converged"].cpu().numpy().astype(bool)
+    fails = (~conv) | (r["flips"].cpu().numpy() != d["true_flips"]).any(1)
+    kms = float(np.mean([s["kernel_ms"] for s in stats]))
+    runs = float(np.mean([s["runs"] for s in stats]))
+    iters = float(np.mean([s["iterations"] for s in stats]))
+    child_runs = runs - shots
+    slot_bytes = 2 * 4 * ((pr.nnz + 3) // 4 * 4)
+    return {"workload": f"W2-hot: the W2 graph and decoder, faults at {mult:g}x the priors "
+                        f"(about {pr.p.sum() * mult:.0f} per shot), {shots} seeded shots",
+            "shots_per_s": shots / (wall / steps), "kernel_ms": kms,
+            "deep_shots": int(stats[-1]["deep_shots"]), "runs": runs, "bp_iterations": iters,
+            "edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
+            "child_runs": child_runs,
+            "slot_bytes_per_child_run": slot_bytes,
+            "slot_traffic_GBs": child_runs * slot_bytes / (kms * 1e-3) / 1e9,
+            "latency_us": {"p50": pct(lat, 50), "p99": pct(lat, 99), "p999": pct(lat, 99.9),
+                           "max": float(lat.max())},
+            "ler": float(fails.mean()), "converged_frac": float(conv.mean())}
+
+
+def w1_leg(bsd, torch, steps=3):
+    """The [[144,12,12]] code-capacity workload (p = 0.05, 1e5 shots, beam width
+    32, 100 iterations split 20 + 10 x 8)."""
+    from bsd_inputs import workloads
+    W = workloads.WORKLOADS["W1"]
+    P = W.params
+    pr = workloads.problem(W.problem_key)
+    code = bsd.Code.from_problem(pr)
+    d = workloads.shots_for(W)
+    syn = torch.from_numpy(np.ascontiguousarray(d["syndromes"])).cuda()
+    prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                          P.num_results, P.alpha, bsd.MODE_BATCHED)
+    stats, wall = timed_calls(code, syn, prm, steps, torch)
+    info = code.info()
+    kms = float(np.mean([s["kernel_ms"] for s in stats]))
+    iters = float(np.mean([s["iterations"] for s in stats]))
+    return {"workload": "W1: [[144,12,12]] BB code capacity, 72 x 144, 432 edges, p = 0.05, "
+                        "1e5 seeded shots, beam width 32, 100 iterations",
+            "shots_per_s": len(syn) / (wall / steps), "kernel_ms": kms,
+            "screened_shots": int(stats[-1]["screened_shots"]),
+            "deep_shots": int(stats[-1]["deep_shots"]),
+            "runs": float(np.mean([s["runs"] for s in stats])), "bp_iterations": iters,
+            "edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
+            "block_threads": info["block"], "grid_blocks": info["grid"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +241,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--plain-shots", type=int, default=10_000)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated extra legs to run after the headline: " + ",".join(LEGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-buffers", action="store_true",
                     help="skip the host-buffer (bus-inclusive) leg, e.g. under a profiler")
@@ -148,6 +256,13 @@ def main():
         print(f"bench.py: this decoder runs on one GPU; --gpus {args.gpus} is not supported "
               f"(shots shard across GPUs with no exchange, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    legs = {x for x in args.legs.split(",") if x}
+    if args.no_cpu_baseline:
+        legs.discard("cpu")
+    if args.no_host_buffers:
+        legs.discard("host")
+    if args.no_serving:
+        legs.discard("serving")
 
     # The serving measurement keeps three persistent decoders on streams of
     # their own: enough hardware queues that none waits behind another kernel.
@@ -184,16 +299,17 @@ def main():
     for _ in range(args.warmup):
         code.decode(syn, prm, out=out)
     torch.cuda.synchronize()
-    kernel_ms, iters = [], []
+    stats = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        r = code.decode(syn, prm, out=out)
-        kernel_ms.append(r["stats"]["kernel_ms"])
-        iters.append(r["stats"]["iterations"])
+        stats.append(code.decode(syn, prm, out=out)["stats"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
     value = shots / (ms_per_step / 1e3)
+    kms = float(np.mean([s["kernel_ms"] for s in stats]))
+    sms = float(np.mean([s["screen_ms"] for s in stats]))
+    iters = float(np.mean([s["iterations"] for s in stats]))
 
     # Per-shot device latency and the logical error rate, from one more call.
     r = code.decode(syn, prm, out=out, latency=True)
@@ -202,40 +318,18 @@ def main():
     conv = out["converged"].cpu().numpy().astype(bool)
     fails = (~conv) | (out["flips"].cpu().numpy() != data["true_flips"]).any(1)
 
-    # The same decode from host buffers (syndromes in and results out over
-    # the bus, staged by the library): the bus-inclusive rate.
-    host_rate = None
-    if not args.no_host_buffers:
-        code.decode_host(syn_h[:1000], prm)
-        th = time.perf_counter()
-        code.decode_host(syn_h, prm)
-        host_rate = shots / (time.perf_counter() - th)
-
-    # Plain form: one kernel launch per BP run, beam bookkeeping on the host.
-    nplain = min(args.plain_shots, shots)
-    prm_plain = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
-                                P.num_results, P.alpha, bsd.MODE_PLAIN)
-    code.decode(syn[:64].contiguous(), prm_plain)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    rp = code.decode(syn[:nplain].contiguous(), prm_plain)
-    torch.cuda.synchronize()
-    plain_rate = nplain / (time.perf_counter() - tp)
-    # per-shot host latency of the plain form (a separate call: it synchronises every shot)
-    nlat = min(nplain, 2000)
-    rl = code.decode(syn[:nlat].contiguous(), prm_plain, latency=True)
-    plat = rl["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0
-    same = bool((rp["corrections"] == out["corrections"][:nplain]).all().item())
-
-    # Roofline of the batched kernel: algorithmic bytes of the two-phase
-    # min-sum form (E read and written per edge, sum_LLR read and written per
-    # column, every iteration of every run) over the kernel's event time.
-    bytes_per_iter = 8 * pr.nnz + 8 * pr.n
-    alg_bytes = float(np.mean(iters)) * bytes_per_iter
-    kms = float(np.mean(kernel_ms))
-    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    # Roofline: the HBM floor of the call's mandatory traffic, syndromes in
+    # (m bytes per shot) and corrections, logical flips and the converged
+    # flag out (n + k + 1 bytes per shot), over the decoding kernels' event
+    # time.  The messages of every BP run live in LDS and never reach HBM.
+    io_bytes_per_shot = pr.m + pr.n + pr.k + 1
+    io_bytes = float(io_bytes_per_shot * shots)
+    achieved = io_bytes / (kms * 1e-3) / 1e9
+    tr = measured_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(alg_bytes)}
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": tr["hbm_bytes_per_call"] if tr else None}
+    assert roofline["frac"] <= 1.0, roofline
 
     res = {
         "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1,
@@ -249,30 +343,66 @@ def main():
                    "initial_iters": P.initial_iters, "iters_per_round": P.iters_per_round,
                    "block_threads": info["block"], "grid_blocks": info["grid"],
                    "lds_bytes": info["lds_bytes"]},
-        "latency_us": {"p50": float(np.percentile(lat_us, 50)),
-                       "p99": float(np.percentile(lat_us, 99)),
-                       "p999": float(np.percentile(lat_us, 99.9)),
+        "latency_us": {"p50": pct(lat_us, 50), "p99": pct(lat_us, 99), "p999": pct(lat_us, 99.9),
                        "max": float(lat_us.max()),
-                       "what": "per shot, device clock from the start of its initial BP run "
-                               "to the write of its result, inside the batched kernel"},
-        "plain": {"shots_per_s": plain_rate, "shots": nplain, "identical_to_batched": same,
-                  "latency_us": {"p50": float(np.percentile(plat, 50)),
-                                 "p99": float(np.percentile(plat, 99)),
-                                 "p999": float(np.percentile(plat, 99.9)),
-                                 "shots": nlat, "what": "host time per shot (its launches and "
-                                                        "transfers), first shots of the batch"}},
-        "batched_over_plain": value / plain_rate,
-        "host_buffers_shots_per_s": host_rate,
+                       "what": "per shot, device clock: its time in the iteration-1 screen plus, "
+                               "for a shot the screen hands on, the persistent decoder's time "
+                               "from its initial BP run to its result write"},
         "kernel_ms": kms,
-        "edge_updates_per_s": float(np.mean(iters)) * pr.nnz / (kms * 1e-3),
-        "bp_iterations_per_step": float(np.mean(iters)),
+        "kernels": {"k_screen_ms": sms, "k_batched_ms": kms - sms,
+                    "screened_shots": int(stats[-1]["screened_shots"]),
+                    "dense_shots": int(shots - stats[-1]["screened_shots"])},
+        "work_rate": {"edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
+                      "bp_iterations_per_step": iters,
+                      "what": "BP iterations x Tanner edges per second of kernel time; a work "
+                              "rate, not a roofline position"},
+        "io_floor": {"bytes_per_shot": io_bytes_per_shot,
+                     "shots_per_s_at_peak": HBM_PEAK_GBS * 1e9 / io_bytes_per_shot},
         "ler": float(fails.mean()),
         "converged_frac": float(conv.mean()),
         "roofline": roofline,
     }
-    if not args.no_serving:
+    if tr:
+        res["traffic_detail"] = {k: tr[k] for k in ("hbm_bytes_per_call", "per_kernel") if k in tr}
+
+    # The same decode from host buffers (syndromes in and results out over
+    # the bus, staged by the library): the bus-inclusive rate.
+    if "host" in legs:
+        code.decode_host(syn_h[:1000], prm)
+        th = time.perf_counter()
+        code.decode_host(syn_h, prm)
+        res["host_buffers_shots_per_s"] = shots / (time.perf_counter() - th)
+
+    # Plain form: one kernel launch per BP run, beam bookkeeping on the host.
+    if "plain" in legs:
+        nplain = min(args.plain_shots, shots)
+        prm_plain = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters,
+                                    P.iters_per_round, P.num_results, P.alpha, bsd.MODE_PLAIN)
+        code.decode(syn[:64].contiguous(), prm_plain)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        rp = code.decode(syn[:nplain].contiguous(), prm_plain)
+        torch.cuda.synchronize()
+        plain_rate = nplain / (time.perf_counter() - tp)
+        # per-shot host latency (a separate call: it synchronises every shot)
+        nlat = min(nplain, 2000)
+        rl = code.decode(syn[:nlat].contiguous(), prm_plain, latency=True)
+        plat = rl["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0
+        same = bool((rp["corrections"] == out["corrections"][:nplain]).all().item())
+        res["plain"] = {"shots_per_s": plain_rate, "shots": nplain, "identical_to_batched": same,
+                        "latency_us": {"p50": pct(plat, 50), "p99": pct(plat, 99),
+                                       "p999": pct(plat, 99.9), "shots": nlat,
+                                       "what": "host time per shot (its launches and "
+                                               "transfers), first shots of the batch"}}
+        res["batched_over_plain"] = value / plain_rate
+
+    if "hot" in legs:
+        res["hot"] = hot_leg(bsd, torch, code, pr, P)
+    if "w1" in legs:
+        res["w1"] = w1_leg(bsd, torch)
+    if "serving" in legs:
         res["serving"] = serving(bsd, torch, code, syn_h, out["corrections"].cpu().numpy())
-    if not args.no_cpu_baseline:
+    if "cpu" in legs:
         res["cpu_baseline"] = cpu_baseline(pr, P, syn_h)
     print(json.dumps(res), flush=True)
 

@@ -18,21 +18,28 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bsd_oracle.cpp")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+# Two builds of the same source: the one the tests use, and one for timing
+# the oracle on the host it runs on (-O3 -march=native; both without FMA
+# contraction or fast-math, so their results are identical).
+_LIB_PATHS = {"tests": os.path.join(_HERE, "liboracle.so"),
+              "native": os.path.join(_HERE, "liboracle_native.so")}
+_OPT = {"tests": ["-O2"], "native": ["-O3", "-march=native"]}
+_LIB_PATH = _LIB_PATHS["tests"]
+_libs = {}
 
 LLR_MAX = 1e30
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, flavour: str = "tests") -> str:
     """Compile the oracle with the host compiler (no FMA contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    path = _LIB_PATHS[flavour]
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        cmd = ["g++", "-std=c++17", *_OPT[flavour], "-ffp-contract=off", "-fno-fast-math", "-fPIC",
                "-shared", "-pthread", _SRC, "-o", tmp]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 class Pair(C.Structure):
@@ -61,13 +68,13 @@ DIAG_DTYPE = np.dtype([("min_abs_post", "f8"), ("min_nextpos_gap", "f8"),
 assert DIAG_DTYPE.itemsize == C.sizeof(ShotDiag)
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = C.CDLL(_LIB_PATH)
+def _load(flavour: str = "tests"):
+    if flavour in _libs:
+        return _libs[flavour]
+    path = _LIB_PATHS[flavour]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=True, flavour=flavour)
+    lib = C.CDLL(path)
     P = C.c_void_p
     i32p = C.POINTER(C.c_int32)
     lib.oracle_problem_create.restype = P
@@ -88,7 +95,7 @@ def _load():
         f.argtypes = [P, C.POINTER(Params), C.c_int64, C.POINTER(C.c_uint8),
                       C.POINTER(C.c_uint8), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8),
                       C.POINTER(ShotDiag), C.c_int32]
-    _lib = lib
+    _libs[flavour] = lib
     return lib
 
 
@@ -107,8 +114,8 @@ def _pairs(pairs):
 class OracleProblem:
     """A decoding problem (H, A, p) loaded into the oracle."""
 
-    def __init__(self, m, n, colptr, rowidx, p, L=None):
-        self._lib = _load()
+    def __init__(self, m, n, colptr, rowidx, p, L=None, flavour="tests"):
+        self._lib = _load(flavour)
         self.m, self.n = int(m), int(n)
         self.colptr = np.ascontiguousarray(colptr, dtype=np.int32)
         self.rowidx = np.ascontiguousarray(rowidx, dtype=np.int32)
@@ -129,8 +136,8 @@ class OracleProblem:
             raise ValueError("oracle rejected the problem (malformed CSC or priors)")
 
     @classmethod
-    def from_problem(cls, pr):
-        return cls(pr.m, pr.n, pr.colptr, pr.rowidx, pr.p, pr.L)
+    def from_problem(cls, pr, flavour="tests"):
+        return cls(pr.m, pr.n, pr.colptr, pr.rowidx, pr.p, pr.L, flavour=flavour)
 
     @property
     def nnz(self):
