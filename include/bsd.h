@@ -96,11 +96,13 @@ typedef enum {
 
 /* Work counters of one bsd_decode_ex call. */
 typedef struct {
-  int64_t runs;         /* BP runs executed (initial and masked) */
-  int64_t iterations;   /* BP iterations summed over runs */
-  int64_t edge_updates; /* iterations x Tanner edges, summed over runs */
-  int64_t deep_shots;   /* shots whose initial BP run did not converge */
-  double kernel_ms;     /* device time of the decoding kernels (HIP events) */
+  int64_t runs;           /* BP runs executed (initial and masked) */
+  int64_t iterations;     /* BP iterations summed over runs */
+  int64_t edge_updates;   /* iterations x Tanner edges, summed over runs */
+  int64_t deep_shots;     /* shots whose initial BP run did not converge */
+  double kernel_ms;       /* device time of the decoding kernels (HIP events) */
+  int64_t screened_shots; /* batched mode: shots finished by the iteration-1 screen */
+  double screen_ms;       /* batched mode: device time of the screen (part of kernel_ms) */
 } bsd_stats;
 
 /* Build a code handle on the current HIP device (Appendix A: the decoding
@@ -125,8 +127,9 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
                            const int32_t* h_rowidx, const double* p, const int32_t* l_colptr,
                            const int32_t* l_rowidx, bsd_code* out);
 
-/* Release a code handle and every device buffer it owns.  BSD_EBUSY if a
- * decode on it is still running. */
+/* Release a code handle and every device buffer it owns, after the work
+ * that asynchronous calls enqueued has finished.  BSD_EBUSY if a call on it
+ * is still in progress in another thread, or a server holds it. */
 bsd_status bsd_code_destroy(bsd_code code);
 
 /* Decode `shots` syndromes with the beam search of Algorithm 3.
@@ -138,16 +141,31 @@ bsd_status bsd_code_destroy(bsd_code code);
  * Buffers may be device memory (decoded in place) or host memory (told apart
  * with hipPointerGetAttributes; then staged through device buffers the code
  * handle keeps, bus transfers included).  They are owned by the caller and
- * must not overlap.  The call returns after the work on `stream` has
- * completed (it reads back a status word).
- * Errors: BSD_EINVAL for bad parameters or syndrome bytes outside {0,1};
- * BSD_ENOMEM when the workspace cannot be allocated; BSD_EDEVICE. */
+ * must not overlap.
+ * Batched mode with every buffer in device memory is asynchronous: the call
+ * returns once the work is enqueued on `stream`, and the outputs are ready
+ * when that work completes.  Syndrome bytes outside {0,1} are then found on
+ * the device and reported by bsd_code_sync.  A handle may be used from
+ * several streams at once (and from several host threads): each stream gets
+ * a workspace of its own, allocated on its first batched call, for at most 8
+ * streams per handle (BSD_EBUSY beyond).  Host buffers and the plain mode
+ * are synchronous.
+ * Errors: BSD_EINVAL for bad parameters (and, when synchronous, syndrome
+ * bytes outside {0,1}); BSD_ENOMEM when the workspace cannot be allocated;
+ * BSD_EDEVICE. */
 bsd_status bsd_decode(bsd_code code, const bsd_params* prm, int64_t shots,
                       const uint8_t* syndromes, uint8_t* corrections, uint8_t* logical_flips,
                       uint8_t* converged, void* stream);
 
-/* As bsd_decode, also filling `stats` (host, may be NULL) and, when
- * `latency_ticks` (uint32 [shots], may be NULL) is given, the
+/* Wait for the work that calls on `stream` enqueued on this code, and
+ * report what an asynchronous call found since the last check: BSD_EINVAL
+ * if syndrome bytes outside {0,1} were seen (reported once), BSD_EDEVICE if
+ * the last call finished fewer shots than it was given.  BSD_OK when the
+ * handle has no work on that stream. */
+bsd_status bsd_code_sync(bsd_code code, void* stream);
+
+/* As bsd_decode, synchronous, also filling `stats` (host, may be NULL) and,
+ * when `latency_ticks` (uint32 [shots], may be NULL) is given, the
  * per-shot decode time in 10 ns ticks: batched mode, the 100 MHz device
  * clock from the start of the shot's initial BP run to the write of its
  * result; plain mode, the host's time for the shot (all its launches and

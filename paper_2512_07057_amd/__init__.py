@@ -41,7 +41,8 @@ class Params(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("runs", C.c_int64), ("iterations", C.c_int64), ("edge_updates", C.c_int64),
-                ("deep_shots", C.c_int64), ("kernel_ms", C.c_double)]
+                ("deep_shots", C.c_int64), ("kernel_ms", C.c_double),
+                ("screened_shots", C.c_int64), ("screen_ms", C.c_double)]
 
 
 class ServeReport(C.Structure):
@@ -81,6 +82,8 @@ def load():
     lib.bsd_code_info.argtypes = [P, C.POINTER(i64), i32p, i32p, i32p]
     lib.bsd_decode.restype = C.c_int
     lib.bsd_decode.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P]
+    lib.bsd_code_sync.restype = C.c_int
+    lib.bsd_code_sync.argtypes = [P, P]
     lib.bsd_decode_ex.restype = C.c_int
     lib.bsd_decode_ex.argtypes = [P, C.POINTER(Params), i64, P, P, P, P, P, C.POINTER(Stats), P]
     lib.bsd_code_autotune.restype = C.c_int
@@ -193,8 +196,10 @@ class Code:
         _check(self._lib.bsd_code_set_alpha_schedule(self._h, len(a),
                                                      a.ctypes.data_as(C.POINTER(C.c_float))))
 
-    def decode(self, syndromes, params: Params, stream=None, latency=False, out=None):
-        """Decode a [shots, m] uint8 CUDA tensor; returns a dict of tensors and stats."""
+    def decode(self, syndromes, params: Params, stream=None, latency=False, out=None, sync=True):
+        """Decode a [shots, m] uint8 CUDA tensor; returns a dict of tensors and stats.
+        With sync=False (batched mode) the call returns once the work is
+        enqueued on `stream` (no stats); input errors are reported by sync()."""
         import torch
         syn = syndromes
         if syn.dtype != torch.uint8 or not syn.is_cuda or not syn.is_contiguous():
@@ -209,6 +214,16 @@ class Code:
                 "flips": torch.empty((shots, max(self.k, 1)), dtype=torch.uint8, device=dev),
                 "converged": torch.empty((shots,), dtype=torch.uint8, device=dev),
             }
+        if not sync:
+            if latency:
+                raise ValueError("latencies need a synchronous call")
+            _check(self._lib.bsd_decode(self._h, C.byref(params), shots, _ptr(syn),
+                                        _ptr(out["corrections"]), _ptr(out["flips"]),
+                                        _ptr(out["converged"]), _stream(stream)))
+            res = dict(out)
+            if self.k == 0:
+                res["flips"] = res["flips"][:, :0]
+            return res
         lat = torch.empty((shots,), dtype=torch.int32, device=dev) if latency else None
         st = Stats()
         rc = self._lib.bsd_decode_ex(self._h, C.byref(params), shots, _ptr(syn),
@@ -223,6 +238,11 @@ class Code:
         if latency:
             res["latency_ticks"] = lat
         return res
+
+    def sync(self, stream=None):
+        """Wait for this code's work on `stream` and raise if an asynchronous
+        call on it since the last check met bad input (bsd_code_sync)."""
+        _check(self._lib.bsd_code_sync(self._h, _stream(stream)))
 
     def decode_host(self, syndromes, params: Params) -> dict:
         """Decode a host uint8 [shots, m] array; the library stages it

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -66,6 +67,36 @@ uint32_t pow2_at_least(uint64_t x) {
 
 }  // namespace
 
+// What batched calls on one stream use: the workspace (queues, contexts,
+// slots), the screen's shot list, events, and the HIP graph of the last call
+// (BSD_FLAG_GRAPH).  Calls on one stream run in stream order, so they share
+// it; calls on different streams have their own and may run concurrently.
+struct Lane {
+  hipStream_t stream = nullptr;
+  std::mutex mu;                   // held while a call enqueues its work
+  BatchWs ws;
+  int32_t* d_list = nullptr;
+  int64_t list_cap = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evs = nullptr;  // evs: end of the screen
+  hipEvent_t done = nullptr;       // recorded after each call's last kernel
+  bool pending = false;            // `done` has been recorded
+  int64_t last_shots = 0;          // shots of the last call (checked by bsd_code_sync)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<char> gkey;
+};
+
+// Tables of iteration 1 for one scaling (see FirstIter): by rank for the
+// persistent decoder, by original row for the screen.
+struct FiTab {
+  float alpha = 0.f;
+  uint4* d_rows = nullptr;
+  uint32_t* d_negbits = nullptr;
+  uint4* d_rowtab = nullptr;
+  FirstIter fi{};
+};
+
 struct bsd_code_s {
   int device = 0;
   DevGraph g{};
@@ -83,26 +114,23 @@ struct bsd_code_s {
   std::vector<float> asched;          // per-iteration scaling (BSD_FLAG_ALPHA_SCHEDULE)
   float* d_asched = nullptr;
   std::vector<uint32_t> cedge_host;   // LDS position | rank << 16, CSC order
-  // First-iteration tables (for one alpha at a time).
-  FirstIter fi{};
-  float fi_alpha = 0.f;
-  bool fi_valid = false;
-  uint4* d_rows = nullptr;
-  uint32_t* d_negbits = nullptr;
-  // Iteration-1 screen: rows in CSR form, each column's rows, the per-row
-  // table of iteration 1 by original row (with fi), and the list of shots it
-  // hands to the dense decoder (grown on demand).
+  // First-iteration tables, one per scaling used so far.
+  std::vector<FiTab*> fi_tabs;
+  // Shared by calls that enqueue work; exclusive for changes to what
+  // kernels in flight read (tables, schedule, launch geometry).
+  std::shared_mutex cfg_mu;
+  // Iteration-1 screen: rows in CSR form and per edge in that order its
+  // column's rows, column and prior.
   bool all_pos = false;  // every prior LLR > 0 in single precision
   int32_t* s_rowptr = nullptr;
   uint4* s_edgerows = nullptr;
   uint2* s_edgecol = nullptr;
   int screen_per_cu = 1;
   int maxdeg_col = 1;
-  uint4* d_rowtab = nullptr;
-  int32_t* d_list = nullptr;
-  int64_t list_cap = 0;
-  // Batched workspace of bsd_decode (grown on demand).
-  BatchWs ws;
+  // Batched decoding: one lane per stream the handle has been used on.
+  std::vector<Lane*> lanes;
+  std::mutex lanes_mu;
+  std::mutex stage_mu;                // the staging buffer of host-memory calls
   size_t slot_stride = 0;
   // Plain-form and single-run workspace.
   char* pslots = nullptr;
@@ -113,12 +141,7 @@ struct bsd_code_s {
   int32_t* h_pinned = nullptr;  // pairs staging [kMaxRounds] + result [4] + error [1]
   std::mutex mu;
   std::atomic<int> busy{0};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // HIP graph of the last batched call (BSD_FLAG_GRAPH).
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<char> gkey;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // plain form's timing
   int grid_frac_half = 0;  // autotuner: use half the resident workgroups
   int ncu = 1;             // compute units of the device
 };
@@ -136,13 +159,37 @@ void ws_free(BatchWs& w) {
   w = BatchWs{};
 }
 
-void drop_graph(bsd_code c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-  c->gkey.clear();
+void drop_graph(Lane* l) {
+  if (l->gexec) hipGraphExecDestroy(l->gexec);
+  if (l->graph) hipGraphDestroy(l->graph);
+  l->gexec = nullptr;
+  l->graph = nullptr;
+  l->gkey.clear();
 }
+
+// Wait until the lane's enqueued work has finished.
+void lane_wait(Lane* l) {
+  if (l->pending) (void)hipEventSynchronize(l->done);
+  l->pending = false;
+}
+
+void lane_free(Lane* l) {
+  lane_wait(l);
+  drop_graph(l);
+  if (l->cap_stream) hipStreamDestroy(l->cap_stream);
+  ws_free(l->ws);
+  hipFree(l->d_list);
+  for (hipEvent_t e : {l->ev0, l->ev1, l->evs, l->done})
+    if (e) hipEventDestroy(e);
+  delete l;
+}
+
+// The lane of `stream`, created on first use (nullptr on failure).
+Lane* get_lane(bsd_code c, hipStream_t stream, bool create = true);
+
+// Every lane idle, and no graph kept: before shared tables or the launch
+// geometry change under work in flight.
+void quiesce(bsd_code c);
 
 // Allocate (or grow) a batched workspace for beam width bw, nctx contexts and
 // num_results results per context.
@@ -163,6 +210,11 @@ bsd_status ws_ensure(const DevGraph& g, BatchWs& w, int bw, int nctx, int num_re
       (void)hipGetLastError();
       return fail(BSD_ENOMEM, "cannot allocate the batched workspace (%zu bytes of slots)", slot_total);
     }
+    if (hipMemset(w.st, 0, sizeof(BatchState)) != hipSuccess) {  // the latched error starts clear
+      ws_free(w);
+      (void)hipGetLastError();
+      return fail(BSD_EDEVICE, "cannot clear the batched workspace");
+    }
     w.nctx = nctx;
     w.bw = bw;
   }
@@ -180,11 +232,51 @@ bsd_status ws_ensure(const DevGraph& g, BatchWs& w, int bw, int nctx, int num_re
   return BSD_OK;
 }
 
-bsd_status ensure_batched(bsd_code c, int bw, int num_results) {
-  const BatchWs before = c->ws;
-  bsd_status st = ws_ensure(c->g, c->ws, bw, c->grid + 64, num_results);
-  if (c->ws.st != before.st || c->ws.results != before.results) drop_graph(c);
+bsd_status ensure_batched(bsd_code c, Lane* l, int bw, int num_results) {
+  const BatchWs before = l->ws;
+  const bool grow = !(before.bw >= bw && before.st && before.nctx >= c->grid + 64) ||
+                    (num_results > 1 &&
+                     before.results_words < (size_t)before.nctx * num_results * c->g.words_n);
+  if (grow) lane_wait(l);  // the lane's earlier kernels may still use the old buffers
+  bsd_status st = ws_ensure(c->g, l->ws, bw, c->grid + 64, num_results);
+  if (l->ws.st != before.st || l->ws.results != before.results) drop_graph(l);
   return st;
+}
+
+void fitab_free(FiTab* t) {
+  hipFree(t->d_rows);
+  hipFree(t->d_negbits);
+  hipFree(t->d_rowtab);
+  delete t;
+}
+
+constexpr size_t kMaxLanes = 8;  // streams one handle decodes on
+
+Lane* get_lane(bsd_code c, hipStream_t stream, bool create) {
+  std::lock_guard<std::mutex> lock(c->lanes_mu);
+  for (Lane* l : c->lanes)
+    if (l->stream == stream) return l;
+  if (!create || c->lanes.size() >= kMaxLanes) return nullptr;
+  Lane* l = new (std::nothrow) Lane;
+  if (!l) return nullptr;
+  l->stream = stream;
+  if (hipEventCreate(&l->ev0) != hipSuccess || hipEventCreate(&l->ev1) != hipSuccess ||
+      hipEventCreate(&l->evs) != hipSuccess ||
+      hipEventCreateWithFlags(&l->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    lane_free(l);
+    return nullptr;
+  }
+  c->lanes.push_back(l);
+  return l;
+}
+
+void quiesce(bsd_code c) {
+  std::lock_guard<std::mutex> lock(c->lanes_mu);
+  for (Lane* l : c->lanes) {
+    lane_wait(l);
+    drop_graph(l);
+  }
 }
 
 bsd_status ensure_plain(bsd_code c, int bw) {
@@ -457,13 +549,19 @@ bsd_status decode_plain(bsd_code c, const bsd_params* p, int64_t shots, const ui
 }
 
 // Check phase of iteration 1 from the priors for a zero syndrome (eq. (1)
-// with E(0) = Lambda), per detector rank, in the kernels' single-precision
+// with E(0) = Lambda), per detector row, in the kernels' single-precision
 // operations: least and second least magnitude of the row, alpha times each,
 // clamped to the message bound; the diagonal index of the least (the first
-// in column order: on a tie both values are equal); the parity of the row's
-// negative priors.
-bsd_status ensure_first(bsd_code c, float alpha) {
-  if (c->fi_valid && c->fi_alpha == alpha) return BSD_OK;
+// in column order: on a tie both values are equal) and its column; the
+// parity of the row's negative priors.  Built once per alpha, under the
+// exclusive configuration lock, and kept until the handle is destroyed, so
+// that kernels in flight never see a table change.
+bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
+  for (const FiTab* t : c->fi_tabs)
+    if (t->alpha == alpha) {
+      *out = t;
+      return BSD_OK;
+    }
   const DevGraph& g = c->g;
   const int n = g.n, m = g.m, nnz = g.nnz;
   const std::vector<int32_t>& cp = c->colptr;
@@ -502,37 +600,65 @@ bsd_status ensure_first(bsd_code c, float alpha) {
     rt[rank] = make_uint4(xb, yb, (uint32_t)argk | ((uint32_t)par << 8) | ((uint32_t)anyneg << 9), 0u);
     rtab[i] = make_uint4(xb, yb, (uint32_t)ecol[rows[i][argk]], 0u);
   }
-  if (!c->d_rows) {
-    if (hipMalloc((void**)&c->d_rows, (size_t)m * sizeof(uint4)) != hipSuccess ||
-        hipMalloc((void**)&c->d_rowtab, (size_t)m * sizeof(uint4)) != hipSuccess ||
-        hipMalloc((void**)&c->d_negbits, neg.size() * 4) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(BSD_ENOMEM, "cannot allocate the first-iteration table");
-    }
+  FiTab* t = new (std::nothrow) FiTab;
+  if (!t) return fail(BSD_ENOMEM, "host allocation failed");
+  t->alpha = alpha;
+  if (dev_upload(&t->d_rows, rt) != hipSuccess || dev_upload(&t->d_rowtab, rtab) != hipSuccess ||
+      dev_upload(&t->d_negbits, neg) != hipSuccess) {
+    (void)hipGetLastError();
+    fitab_free(t);
+    return fail(BSD_ENOMEM, "cannot allocate the first-iteration table");
   }
-  HIP_OR_FAIL(hipMemcpy(c->d_rows, rt.data(), (size_t)m * sizeof(uint4), hipMemcpyHostToDevice));
-  HIP_OR_FAIL(hipMemcpy(c->d_rowtab, rtab.data(), (size_t)m * sizeof(uint4), hipMemcpyHostToDevice));
-  HIP_OR_FAIL(hipMemcpy(c->d_negbits, neg.data(), neg.size() * 4, hipMemcpyHostToDevice));
-  c->fi.rows = c->d_rows;
-  c->fi.negbits = c->d_negbits;
-  c->fi.enabled = 1;
-  c->fi_alpha = alpha;
-  c->fi_valid = true;
-  drop_graph(c);
+  t->fi.rows = t->d_rows;
+  t->fi.negbits = t->d_negbits;
+  t->fi.enabled = 1;
+  c->fi_tabs.push_back(t);
+  *out = t;
   return BSD_OK;
 }
 
+bool needs_first(const bsd_params* p) {
+  return !(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1;
+}
+
+// Iteration 1's scaling (configuration lock held).
+float first_alpha(const bsd_code c, const bsd_params* p) {
+  return (p->flags & BSD_FLAG_ALPHA_SCHEDULE) && !c->asched.empty() ? c->asched[0] : p->alpha;
+}
+
+// The table a call needs, or nullptr (configuration lock held, shared or exclusive).
+const FiTab* find_first(const bsd_code c, const bsd_params* p) {
+  if (!needs_first(p)) return nullptr;
+  const float a1 = first_alpha(c, p);
+  for (const FiTab* t : c->fi_tabs)
+    if (t->alpha == a1) return t;
+  return nullptr;
+}
+
+// Runs fn(table) with the configuration lock shared and the iteration-1
+// table the call needs (built first, under the exclusive lock, if missing).
+template <class F>
+bsd_status with_tables(bsd_code c, const bsd_params* p, F fn) {
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    {
+      std::shared_lock<std::shared_mutex> cfg(c->cfg_mu);
+      const FiTab* ft = find_first(c, p);
+      if (ft || !needs_first(p)) return fn(ft);
+    }
+    std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
+    const FiTab* t = nullptr;
+    bsd_status st = build_first(c, first_alpha(c, p), &t);
+    if (st != BSD_OK) return st;
+  }
+  return fail(BSD_EBUSY, "the scaling schedule changed during the call");
+}
+
 // Kernel arguments common to every batched launch on workspace w.
-bsd_status batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, BatchArgs* out) {
+BatchArgs batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, const FiTab* ft) {
   BatchArgs a{};
   a.g = c->g;
-  const bool sched = (p->flags & BSD_FLAG_ALPHA_SCHEDULE) != 0;
-  if (!(p->flags & BSD_FLAG_DENSE_FIRST) && p->initial_iters >= 1) {
-    bsd_status st = ensure_first(c, sched ? c->asched[0] : p->alpha);  // iteration 1's scaling
-    if (st != BSD_OK) return st;
-    a.fi = c->fi;
-  }
-  if (sched) {
+  if (ft) a.fi = ft->fi;
+  if (p->flags & BSD_FLAG_ALPHA_SCHEDULE) {
     a.alpha_sched = c->d_asched;
     a.n_sched = (int32_t)c->asched.size();
   }
@@ -554,8 +680,7 @@ bsd_status batch_args(bsd_code c, const BatchWs& w, const bsd_params* p, BatchAr
   a.slots = w.slots;
   a.slot_stride = slot_bytes(c->g);
   a.slots_per_ctx = 3 * w.bw + 1;
-  *out = a;
-  return BSD_OK;
+  return a;
 }
 
 // Whether a batched call starts with the sparse screen of iteration 1: the
@@ -567,7 +692,7 @@ bool use_screen(const bsd_code c, const bsd_params* p, const BatchArgs& a) {
          p->num_results == 1 && c->all_pos && a.fi.enabled;
 }
 
-ScreenArgs screen_args(const bsd_code c, const BatchArgs& a) {
+ScreenArgs screen_args(const bsd_code c, const BatchArgs& a, const FiTab* ft) {
   const DevGraph& g = c->g;
   ScreenArgs sa{};
   sa.m = g.m;
@@ -581,7 +706,7 @@ ScreenArgs screen_args(const bsd_code c, const BatchArgs& a) {
   sa.row_ptr = c->s_rowptr;
   sa.edge_rows = c->s_edgerows;
   sa.edge_col = c->s_edgecol;
-  sa.row_tab = c->d_rowtab;
+  sa.row_tab = ft ? ft->d_rowtab : nullptr;
   sa.lmask = g.lmask;
   sa.shots = a.shots;
   sa.syn = a.syn;
@@ -601,14 +726,15 @@ int screen_grid(const bsd_code c, int64_t shots) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)c->screen_per_cu * c->ncu));
 }
 
-bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
-                          uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
-                          bsd_stats* stats, uint32_t* lat) {
-  bsd_status st = ensure_batched(c, p->beam_width, p->num_results);
+// One batched call on lane l (its mutex and the configuration lock held).
+// With `async` it returns once the work is enqueued on the lane's stream.
+bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab* ft,
+                          int64_t shots, const uint8_t* syn, uint8_t* corr, uint8_t* flips,
+                          uint8_t* conv, bool async, bsd_stats* stats, uint32_t* lat) {
+  const hipStream_t s = l->stream;
+  bsd_status st = ensure_batched(c, l, p->beam_width, p->num_results);
   if (st != BSD_OK) return st;
-  BatchArgs a{};
-  st = batch_args(c, c->ws, p, &a);
-  if (st != BSD_OK) return st;
+  BatchArgs a = batch_args(c, l->ws, p, ft);
   a.shots = shots;
   a.syn = syn;
   a.corr = corr;
@@ -617,20 +743,21 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
   a.lat = lat;
   const bool screen = use_screen(c, p, a);
   if (screen) {
-    if (c->list_cap < shots) {
-      hipFree(c->d_list);
-      c->d_list = nullptr;
-      c->list_cap = 0;
-      if (hipMalloc((void**)&c->d_list, (size_t)shots * 4) != hipSuccess) {
+    if (l->list_cap < shots) {
+      lane_wait(l);
+      hipFree(l->d_list);
+      l->d_list = nullptr;
+      l->list_cap = 0;
+      if (hipMalloc((void**)&l->d_list, (size_t)shots * 4) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BSD_ENOMEM, "cannot allocate the screen's shot list (%lld shots)", (long long)shots);
       }
-      c->list_cap = shots;
-      drop_graph(c);
+      l->list_cap = shots;
+      drop_graph(l);
     }
-    a.shot_list = c->d_list;
+    a.shot_list = l->d_list;
   }
-  const ScreenArgs sa = screen_args(c, a);
+  const ScreenArgs sa = screen_args(c, a, ft);
   const int sgrid = screen_grid(c, shots);
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
@@ -638,47 +765,64 @@ bsd_status decode_batched(bsd_code c, const bsd_params* p, int64_t shots, const 
     std::memcpy(key.data(), &a, sizeof a);
     const int geo[3] = {c->grid, c->block, c->cpt};
     std::memcpy(key.data() + sizeof a, geo, sizeof geo);
-    if (!c->gexec || key != c->gkey) {
-      drop_graph(c);
-      if (!c->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-      HIP_OR_FAIL(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t e1 = launch_batch_reset(a, c->cap_stream);
-      if (e1 == hipSuccess && screen) e1 = launch_screen(sa, sgrid, c->cap_stream);
-      hipError_t e2 = launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, c->cap_stream);
+    if (!l->gexec || key != l->gkey) {
+      drop_graph(l);
+      if (!l->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&l->cap_stream, hipStreamNonBlocking));
+      HIP_OR_FAIL(hipStreamBeginCapture(l->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = launch_batch_reset(a, l->cap_stream);
+      if (e1 == hipSuccess && screen) e1 = launch_screen(sa, sgrid, l->cap_stream);
+      hipError_t e2 = launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, l->cap_stream);
       hipGraph_t gr = nullptr;
-      hipError_t e3 = hipStreamEndCapture(c->cap_stream, &gr);
+      hipError_t e3 = hipStreamEndCapture(l->cap_stream, &gr);
       if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         if (gr) hipGraphDestroy(gr);
         return fail(BSD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3));
       }
-      c->graph = gr;
-      HIP_OR_FAIL(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-      c->gkey = key;
+      l->graph = gr;
+      HIP_OR_FAIL(hipGraphInstantiate(&l->gexec, l->graph, nullptr, nullptr, 0));
+      l->gkey = key;
     }
-    HIP_OR_FAIL(hipEventRecord(c->ev0, s));
-    HIP_OR_FAIL(hipGraphLaunch(c->gexec, s));
-    HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+    HIP_OR_FAIL(hipEventRecord(l->ev0, s));
+    HIP_OR_FAIL(hipGraphLaunch(l->gexec, s));
+    HIP_OR_FAIL(hipEventRecord(l->ev1, s));
   } else {
     HIP_OR_FAIL(launch_batch_reset(a, s));
-    HIP_OR_FAIL(hipEventRecord(c->ev0, s));
+    HIP_OR_FAIL(hipEventRecord(l->ev0, s));
     if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, s));
+    HIP_OR_FAIL(hipEventRecord(l->evs, s));
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
-    HIP_OR_FAIL(hipEventRecord(c->ev1, s));
+    HIP_OR_FAIL(hipEventRecord(l->ev1, s));
   }
-  HIP_OR_FAIL(hipMemcpyAsync(c->ws.st_host, c->ws.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipEventRecord(l->done, s));
+  l->pending = true;
+  l->last_shots = shots;
+  if (async) return BSD_OK;
+  HIP_OR_FAIL(hipMemcpyAsync(l->ws.st_host, l->ws.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
-  const BatchState& h = *c->ws.st_host;
-  if (h.error) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  l->pending = false;
+  BatchState& h = *l->ws.st_host;
+  if (h.error) {  // reported here, so not again by bsd_code_sync
+    h.error = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(l->ws.st, l->ws.st_host, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
+  }
   if (h.done != (unsigned long long)shots)
     return fail(BSD_EDEVICE, "batched decoder finished %llu of %lld shots", h.done, (long long)shots);
   if (stats) {
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    float ms = 0.f, sms = 0.f;
+    (void)hipEventElapsedTime(&ms, l->ev0, l->ev1);
     stats->runs = (int64_t)h.runs;
     stats->iterations = (int64_t)h.iterations;
     stats->edge_updates = (int64_t)h.iterations * c->g.nnz;
     stats->deep_shots = (int64_t)h.deep;
     stats->kernel_ms = ms;
+    if (screen) {
+      // (a graph replay is timed as a whole: screen_ms stays 0)
+      if (!(p->flags & BSD_FLAG_GRAPH)) (void)hipEventElapsedTime(&sms, l->ev0, l->evs);
+      stats->screened_shots = shots - (int64_t)h.listed;
+      stats->screen_ms = sms;
+    }
   }
   return BSD_OK;
 }
@@ -697,7 +841,7 @@ bsd_status set_geometry(bsd_code c, int block, int half) {
   if (he != hipSuccess || per_cu < 1)
     return fail(BSD_EDEVICE, "occupancy query failed: %s (blocks per CU %d)", hipGetErrorString(he), per_cu);
   const int grid = half && per_cu > 1 ? (per_cu / 2) * ncu : per_cu * ncu;
-  if (grid != c->grid || block != c->block) drop_graph(c);
+  if (grid != c->grid || block != c->block) quiesce(c);
   c->ncu = ncu;
   c->block = block;
   c->cpt = cpt;
@@ -927,23 +1071,24 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
 
 bsd_status bsd_code_destroy(bsd_code c) {
   if (!c) return BSD_OK;
-  if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
-  drop_graph(c);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  {
+    std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
+    if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
+  }
+  // Work enqueued by asynchronous calls finishes before its memory goes.
+  for (Lane* l : c->lanes) lane_free(l);
+  c->lanes.clear();
+  for (FiTab* t : c->fi_tabs) fitab_free(t);
+  c->fi_tabs.clear();
   hipFree(c->d_stage);
-  hipFree(c->d_rows);
   hipFree(c->d_resbits);
   hipFree(c->d_asched);
   hipFree(c->u_colptr);
   hipFree(c->u_rowptr);
   hipFree(c->u_rowedge);
-  hipFree(c->d_negbits);
-  hipFree(c->d_rowtab);
   hipFree(c->s_rowptr);
   hipFree(c->s_edgerows);
   hipFree(c->s_edgecol);
-  hipFree(c->d_list);
-  ws_free(c->ws);
   for (void* p : c->owned) hipFree(p);
   hipFree(c->pslots);
   hipFree(c->d_pairs);
@@ -962,9 +1107,9 @@ bsd_status bsd_code_set_alpha_schedule(bsd_code c, int32_t n, const float* alpha
   for (int i = 0; i < n; ++i)
     if (!(alphas[i] > 0.f) || !std::isfinite(alphas[i]))
       return fail(BSD_EINVAL, "scaling %d must be positive and finite", i);
-  std::lock_guard<std::mutex> lock(c->mu);
+  std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
   if (c->busy.load() != 0) return fail(BSD_EBUSY, "code handle is in use");
-  drop_graph(c);
+  quiesce(c);  // asynchronous calls may still read the old schedule
   hipFree(c->d_asched);
   c->d_asched = nullptr;
   c->asched.assign(alphas, alphas + n);
@@ -1003,9 +1148,11 @@ bool is_device_ptr(const void* ptr) {
 
 // Host buffers: copy the syndromes in and the outputs back through device
 // buffers of the code handle (grown on demand); synchronous.
-bsd_status decode_staged(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
-                         uint8_t* corr, uint8_t* flips, uint8_t* conv, hipStream_t s,
-                         bsd_stats* stats, uint32_t* lat) {
+// Configuration lock shared and c->stage_mu held; the lane's mutex (batched)
+// or c->mu (plain) is taken here.
+bsd_status decode_staged(bsd_code c, Lane* l, const FiTab* ft, const bsd_params* p, int64_t shots,
+                         const uint8_t* syn, uint8_t* corr, uint8_t* flips, uint8_t* conv,
+                         hipStream_t s, bsd_stats* stats, uint32_t* lat) {
   const DevGraph& g = c->g;
   const size_t need = (size_t)shots * (g.m + g.n + std::max(g.k, 1) + 1 + 4) + 64;
   if (c->stage_bytes < need) {
@@ -1017,7 +1164,6 @@ bsd_status decode_staged(bsd_code c, const bsd_params* p, int64_t shots, const u
       return fail(BSD_ENOMEM, "cannot allocate %zu bytes to stage host buffers", need);
     }
     c->stage_bytes = need;
-    drop_graph(c);
   }
   uint8_t* ds = c->d_stage;
   uint8_t* dc = ds + (size_t)shots * g.m;
@@ -1027,9 +1173,14 @@ bsd_status decode_staged(bsd_code c, const bsd_params* p, int64_t shots, const u
   const bool dev_syn = is_device_ptr(syn);
   HIP_OR_FAIL(hipMemcpyAsync(ds, syn, (size_t)shots * g.m,
                              dev_syn ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-  bsd_status st = p->mode == BSD_MODE_PLAIN
-                      ? decode_plain(c, p, shots, ds, dc, df, dv, s, stats, lat ? dl : nullptr)
-                      : decode_batched(c, p, shots, ds, dc, df, dv, s, stats, lat ? dl : nullptr);
+  bsd_status st;
+  if (p->mode == BSD_MODE_PLAIN) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    st = decode_plain(c, p, shots, ds, dc, df, dv, s, stats, lat ? dl : nullptr);
+  } else {
+    std::lock_guard<std::mutex> lock(l->mu);
+    st = decode_batched(c, l, p, ft, shots, ds, dc, df, dv, false, stats, lat ? dl : nullptr);
+  }
   if (st != BSD_OK) return st;
   HIP_OR_FAIL(hipMemcpyAsync(corr, dc, (size_t)shots * g.n, hipMemcpyDefault, s));
   if (g.k > 0) HIP_OR_FAIL(hipMemcpyAsync(flips, df, (size_t)shots * g.k, hipMemcpyDefault, s));
@@ -1055,7 +1206,6 @@ bsd_status bsd_decode_ex(bsd_code c, const bsd_params* p, int64_t shots, const u
   if (shots > (int64_t)0x7FFFFFFF) return fail(BSD_EINVAL, "at most 2^31-1 shots per call");
   if (!syn || !corr || !conv || (c->g.k > 0 && !flips))
     return fail(BSD_EINVAL, "syndromes, corrections, logical_flips and converged are required");
-  std::lock_guard<std::mutex> lock(c->mu);
   c->busy++;
   int dev_prev = 0;
   (void)hipGetDevice(&dev_prev);
@@ -1063,15 +1213,54 @@ bsd_status bsd_decode_ex(bsd_code c, const bsd_params* p, int64_t shots, const u
   hipStream_t s = (hipStream_t)stream;
   const bool staged = !is_device_ptr(syn) || !is_device_ptr(corr) || !is_device_ptr(conv) ||
                       (c->g.k > 0 && !is_device_ptr(flips)) || (lat && !is_device_ptr(lat));
-  if (staged) {
-    st = decode_staged(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+  // Device buffers in batched mode with neither stats nor latencies asked
+  // for: return once the work is enqueued (errors: bsd_code_sync).
+  const bool async = !staged && !stats && !lat && p->mode == BSD_MODE_BATCHED;
+  Lane* l = p->mode == BSD_MODE_BATCHED ? get_lane(c, s) : nullptr;
+  if (p->mode == BSD_MODE_BATCHED && !l) {
+    st = fail(BSD_EBUSY, "no workspace for another stream (at most %zu streams per code)", kMaxLanes);
   } else {
-    st = p->mode == BSD_MODE_PLAIN ? decode_plain(c, p, shots, syn, corr, flips, conv, s, stats, lat)
-                                   : decode_batched(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+    std::unique_lock<std::mutex> stage;
+    if (staged) stage = std::unique_lock<std::mutex>(c->stage_mu);
+    st = with_tables(c, p, [&](const FiTab* ft) -> bsd_status {
+      if (staged) return decode_staged(c, l, ft, p, shots, syn, corr, flips, conv, s, stats, lat);
+      if (p->mode == BSD_MODE_PLAIN) {
+        std::lock_guard<std::mutex> lock(c->mu);
+        return decode_plain(c, p, shots, syn, corr, flips, conv, s, stats, lat);
+      }
+      std::lock_guard<std::mutex> lock(l->mu);
+      return decode_batched(c, l, p, ft, shots, syn, corr, flips, conv, async, stats, lat);
+    });
   }
   (void)hipSetDevice(dev_prev);
   c->busy--;
   return st;
+}
+
+bsd_status bsd_code_sync(bsd_code c, void* stream) {
+  if (!c) return fail(BSD_EINVAL, "code is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  Lane* l = get_lane(c, s, false);
+  if (!l) return BSD_OK;
+  std::shared_lock<std::shared_mutex> cfg(c->cfg_mu);
+  std::lock_guard<std::mutex> lock(l->mu);
+  if (!l->ws.st) return BSD_OK;
+  HIP_OR_FAIL(hipMemcpyAsync(l->ws.st_host, l->ws.st, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  l->pending = false;
+  BatchState& h = *l->ws.st_host;
+  const bool bad = h.error || h.sticky;
+  const unsigned long long done = h.done;
+  if (bad) {  // report once
+    h.error = 0;
+    h.sticky = 0;
+    HIP_OR_FAIL(hipMemcpyAsync(l->ws.st, l->ws.st_host, sizeof(BatchState), hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1 (a call on this stream since the last check)");
+  }
+  if (l->last_shots && done != (unsigned long long)l->last_shots)
+    return fail(BSD_EDEVICE, "batched decoder finished %llu of %lld shots", done, (long long)l->last_shots);
+  return BSD_OK;
 }
 
 bsd_status bsd_decode(bsd_code c, const bsd_params* p, int64_t shots, const uint8_t* syn,
@@ -1162,7 +1351,7 @@ bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, con
       bool hit = false;
       while (fscanf(f, "%llx %d %d %f", &key, &b, &half, &ms) == 4) {
         if (key == h) {
-          std::lock_guard<std::mutex> lock(c->mu);
+          std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
           if (set_geometry(c, b, half) == BSD_OK) {
             hit = true;
             if (out_ms) *out_ms = ms;
@@ -1195,7 +1384,7 @@ bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, con
   for (int b = 64; b <= 1024 && st == BSD_OK; b *= 2) {
     for (int half = 0; half <= 1; ++half) {
       {
-        std::lock_guard<std::mutex> lock(c->mu);
+        std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
         if (set_geometry(c, b, half) != BSD_OK) break;
         if (half && !c->grid_frac_half) break;
       }
@@ -1216,7 +1405,7 @@ bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, con
   hipFree(flips);
   hipFree(conv);
   {
-    std::lock_guard<std::mutex> lock(c->mu);
+    std::unique_lock<std::shared_mutex> cfg(c->cfg_mu);
     bsd_status s2 = set_geometry(c, best_b, best_h);
     if (st == BSD_OK) st = s2;
   }
@@ -1408,7 +1597,13 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
   std::vector<BatchArgs> args(ncodes);
   for (int i = 0; i < ncodes; ++i) {
     ServeQ& q = s->q[i];
-    bsd_status st = batch_args(q.code, q.ws, &q.prm, &args[i]);
+    const FiTab* ft = nullptr;
+    bsd_status st = BSD_OK;
+    if (needs_first(&q.prm)) {  // kept until the code is destroyed, which the server prevents
+      std::unique_lock<std::shared_mutex> cfg(q.code->cfg_mu);
+      st = build_first(q.code, first_alpha(q.code, &q.prm), &ft);
+    }
+    if (st == BSD_OK) args[i] = batch_args(q.code, q.ws, &q.prm, ft);
     hipError_t he = st == BSD_OK ? set_kernel_limits(q.code->cpt, q.code->pw, q.code->lds) : hipSuccess;
     if (st == BSD_OK && he != hipSuccess) st = fail(BSD_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(he));
     if (st != BSD_OK) {

@@ -101,7 +101,7 @@ struct BatchState {
   uint32_t stop;           // nonzero: end the kernel
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
   int32_t listed;          // shots the iteration-1 screen handed to the dense decoder
-  int32_t pad0;
+  uint32_t sticky;         // errors of earlier calls on this workspace, until reported
 };
 
 // The check phase of iteration 1 in a run from the priors with no masked
@@ -208,7 +208,7 @@ struct ScreenArgs {
 };
 constexpr int kScreenBlock = 512;        // eight shots in flight per workgroup
 constexpr int kScreenMaxFlipped = 64;    // more flipped detectors: dense decoder
-constexpr int kScreenMaxCand = 1024;     // more (detector, column) pairs: dense decoder
+constexpr int kScreenMaxCand = 2048;     // more (detector, column) pairs: dense decoder
 constexpr int kScreenMaxSet = 64;        // more set decisions: dense decoder
 size_t screen_lds_bytes(int m);
 int screen_blocks_per_cu(int m);

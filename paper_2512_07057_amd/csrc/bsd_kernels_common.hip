@@ -16,6 +16,7 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->runs = 0;
     a.st->iterations = 0;
     a.st->deep = 0;
+    a.st->sticky |= a.st->error;
     a.st->error = 0;
     a.st->started_wgs = 0;
     a.st->work.head = 0;

@@ -1,0 +1,153 @@
+"""bsd_decode with device buffers is asynchronous on its stream, and one code
+handle may be used from several streams and host threads at once.  Bars:
+outputs identical to the same batches decoded one after the other
+synchronously; the asynchronous call returns before its work is done;
+syndrome errors are reported by bsd_code_sync, once; destroying a handle
+waits for its enqueued work."""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import gpu_common as gc
+from bsd_inputs import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bsd():
+    import paper_2512_07057_amd as m
+    m.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
+
+
+def _params(bsd, P, flags=0):
+    return bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                           P.num_results, P.alpha, bsd.MODE_BATCHED, flags)
+
+
+def _np(out):
+    return {k: out[k].cpu().numpy() for k in ("corrections", "flips", "converged")}
+
+
+def _empty(code, shots):
+    return {"corrections": torch.empty((shots, code.n), dtype=torch.uint8, device="cuda"),
+            "flips": torch.empty((shots, max(code.k, 1)), dtype=torch.uint8, device="cuda"),
+            "converged": torch.empty((shots,), dtype=torch.uint8, device="cuda")}
+
+
+def _same(a, b, what):
+    for k in ("corrections", "flips", "converged"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"{what}: {k}")
+
+
+def test_two_streams_concurrently(bsd):
+    """Two batches of each workload enqueued on two streams of one handle,
+    back to back without waiting, equal the same batches decoded in turn."""
+    for wl, shots in (("W1", 40_000), ("W2", 50_000)):
+        W = workloads.WORKLOADS[wl]
+        code = bsd.Code.from_problem(gc.problem(W.problem_key))
+        prm = _params(bsd, W.params)
+        a = torch.from_numpy(gc.samples(wl, shots, seed=41)["syndromes"]).cuda()
+        b = torch.from_numpy(gc.samples(wl, shots, seed=42)["syndromes"]).cuda()
+        ref_a, ref_b = _np(code.decode(a, prm)), _np(code.decode(b, prm))
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        oa, ob = _empty(code, shots), _empty(code, shots)
+        t0 = time.perf_counter()
+        code.decode(a, prm, stream=s1, out=oa, sync=False)
+        code.decode(b, prm, stream=s2, out=ob, sync=False)
+        t_enqueue = time.perf_counter() - t0
+        code.sync(s1)
+        code.sync(s2)
+        t_all = time.perf_counter() - t0
+        gc.log(wl, "enqueue ms", t_enqueue * 1e3, "both done ms", t_all * 1e3)
+        _same(_np(oa), ref_a, f"{wl} stream 1")
+        _same(_np(ob), ref_b, f"{wl} stream 2")
+        if wl == "W1":  # ~40 ms of work per batch: the calls return well before it is done
+            assert t_enqueue < 0.5 * t_all
+        # repeat on the same two streams: each keeps its own workspace
+        for rep in range(2):
+            code.decode(b, prm, stream=s1, out=oa, sync=False)
+            code.decode(a, prm, stream=s2, out=ob, sync=False)
+            code.sync(s1)
+            code.sync(s2)
+            _same(_np(oa), ref_b, f"{wl} swap {rep}")
+            _same(_np(ob), ref_a, f"{wl} swap {rep}")
+        code.close()
+
+
+def test_host_threads_share_a_handle(bsd):
+    """Four host threads, each with its own stream, decode different batches
+    through one handle, asynchronously and synchronously in turn."""
+    W = workloads.WORKLOADS["W0"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    prm = _params(bsd, W.params)
+    batches = [torch.from_numpy(gc.samples("W0", 3000, seed=50 + i)["syndromes"]).cuda()
+               for i in range(4)]
+    refs = [_np(code.decode(x, prm)) for x in batches]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(i):
+        try:
+            st = torch.cuda.Stream()
+            for rep in range(4):
+                x = batches[(i + rep) % 4]
+                if rep % 2:
+                    with torch.cuda.stream(st):
+                        r = _np(code.decode(x, prm, stream=st))
+                else:
+                    o = _empty(code, x.shape[0])
+                    code.decode(x, prm, stream=st, out=o, sync=False)
+                    code.sync(st)
+                    r = _np(o)
+                _same(r, refs[(i + rep) % 4], f"thread {i} rep {rep}")
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors[0]
+
+
+def test_async_errors_reported_by_sync(bsd):
+    W = workloads.WORKLOADS["W0"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    prm = _params(bsd, W.params)
+    syn = torch.from_numpy(gc.samples("W0", 500, seed=60)["syndromes"]).cuda()
+    bad = syn.clone()
+    bad[7, 3] = 2
+    code.decode(bad, prm, out=_empty(code, 500), sync=False)  # returns: no check yet
+    code.decode(syn, prm, out=_empty(code, 500), sync=False)  # a later good call keeps the error
+    with pytest.raises(bsd.BsdError) as ei:
+        code.sync()
+    assert ei.value.status == bsd.BSD_EINVAL
+    code.sync()  # reported once
+    # a synchronous call reports its own error at once
+    with pytest.raises(bsd.BsdError):
+        code.decode(bad, prm)
+    code.sync()
+
+
+def test_destroy_waits_for_enqueued_work(bsd):
+    W = workloads.WORKLOADS["W1"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    prm = _params(bsd, W.params)
+    syn = torch.from_numpy(gc.samples("W1", 30_000, seed=70)["syndromes"]).cuda()
+    ref = _np(code.decode(syn, prm))
+    out = _empty(code, 30_000)
+    out["corrections"].fill_(9)
+    code.decode(syn, prm, out=out, sync=False)
+    code.close()  # waits for the kernels before freeing their workspace
+    torch.cuda.synchronize()
+    _same(_np(out), ref, "after destroy")
