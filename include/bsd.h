@@ -242,9 +242,18 @@ bsd_status bsd_code_info(bsd_code code, int64_t* nnz, int32_t* block_threads, in
  * every workgroup of one is resident before launching the next; a decoder
  * that does not get there within 5 s makes creation fail with BSD_EDEVICE.
  * A server holds its codes (bsd_code_destroy returns BSD_EBUSY meanwhile).
- * Its kernels end when it is destroyed, or on their own after about 20 s
- * without work. */
+ * Its kernels end when it is destroyed.  A decoder also ends on its own
+ * after a stretch without work (20 s by default, bsd_server_opts.idle_ms),
+ * giving its compute units back; the next submit or poll on that code
+ * starts it again, with every earlier request and context intact. */
 typedef struct bsd_server_s* bsd_server;
+
+/* Options of bsd_server_create_ex (zero-initialised = defaults). */
+typedef struct {
+  int64_t ring_bytes; /* pinned host memory for the request rings (0 = 64 MiB) */
+  int64_t idle_ms;    /* a decoder ends after this long without work, 1..40000
+                         (0 = 20 s); a later request starts it again */
+} bsd_server_opts;
 
 /* Create a server for ncodes (1..8) distinct codes of the current device.
  *   params       host, [ncodes]: decoder of each code (batched mode)
@@ -255,9 +264,24 @@ typedef struct bsd_server_s* bsd_server;
 bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
                              const int32_t* grid_blocks, int64_t ring_bytes, bsd_server* out);
 
+/* As bsd_server_create, with options (may be NULL).  Also BSD_EINVAL when
+ * ncodes exceeds the hardware queues HIP gives the process
+ * (GPU_MAX_HW_QUEUES, default 4), since every decoder needs one. */
+bsd_status bsd_server_create_ex(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
+                                const int32_t* grid_blocks, const bsd_server_opts* opts,
+                                bsd_server* out);
+
+/* State of one code's decoder: whether its kernel is running now, and how
+ * many times it has been launched (1 + relaunches after idle exits).  Either
+ * pointer may be NULL. */
+bsd_status bsd_server_info(bsd_server s, int32_t code, int32_t* running, int64_t* launches);
+
 /* Submit one syndrome (host, uint8 [m], copied) for code `code`; `ticket`
  * receives the request's number within that code.  BSD_EBUSY when the ring
- * row it needs is still held by an earlier request (poll that one first). */
+ * row it needs is still held by an earlier request (poll that one first).
+ * Starts the code's decoder again if it has ended after its idle limit
+ * (BSD_EDEVICE if it cannot get every workgroup running within 5 s; the
+ * request stays published and a later poll tries again). */
 bsd_status bsd_server_submit(bsd_server s, int32_t code, const uint8_t* syndrome, int64_t* ticket);
 
 /* If request `ticket` of `code` has finished, copy its outputs (host, may be

@@ -54,6 +54,10 @@ class ServeReport(C.Structure):
                 ("admission_waits", C.c_int64)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("ring_bytes", C.c_int64), ("idle_ms", C.c_int64)]
+
+
 def exported_symbols_from_header(path: str = HEADER) -> list[str]:
     text = open(path).read()
     return sorted(set(re.findall(r"\b(bsd_[a-z_]+)\s*\(", text)))
@@ -91,6 +95,11 @@ def load():
                                       C.POINTER(C.c_float), P]
     lib.bsd_server_create.restype = C.c_int
     lib.bsd_server_create.argtypes = [i32, C.POINTER(P), C.POINTER(Params), i32p, i64, C.POINTER(P)]
+    lib.bsd_server_create_ex.restype = C.c_int
+    lib.bsd_server_create_ex.argtypes = [i32, C.POINTER(P), C.POINTER(Params), i32p,
+                                         C.POINTER(ServerOpts), C.POINTER(P)]
+    lib.bsd_server_info.restype = C.c_int
+    lib.bsd_server_info.argtypes = [P, i32, i32p, C.POINTER(i64)]
     lib.bsd_server_submit.restype = C.c_int
     lib.bsd_server_submit.argtypes = [P, i32, P, C.POINTER(i64)]
     lib.bsd_server_poll.restype = C.c_int
@@ -304,7 +313,7 @@ class Server:
     """Persistent GPU decoders for several resident codes, fed continuously
     (bsd_server_*).  Codes must outlive the server."""
 
-    def __init__(self, codes, params, grid_blocks=None, ring_bytes=0):
+    def __init__(self, codes, params, grid_blocks=None, ring_bytes=0, idle_ms=0):
         self._lib = load()
         self.codes = list(codes)
         n = len(self.codes)
@@ -312,8 +321,15 @@ class Server:
         prm = (Params * n)(*params)
         grid = (C.c_int32 * n)(*(grid_blocks or [0] * n))
         h = C.c_void_p()
-        _check(self._lib.bsd_server_create(n, hs, prm, grid, int(ring_bytes), C.byref(h)))
+        opts = ServerOpts(int(ring_bytes), int(idle_ms))
+        _check(self._lib.bsd_server_create_ex(n, hs, prm, grid, C.byref(opts), C.byref(h)))
         self._h = h
+
+    def info(self, code: int) -> dict:
+        """Whether the code's decoder kernel is running, and its launch count."""
+        running, launches = C.c_int32(), C.c_int64()
+        _check(self._lib.bsd_server_info(self._h, int(code), C.byref(running), C.byref(launches)))
+        return {"running": bool(running.value), "launches": launches.value}
 
     def submit(self, code: int, syndrome) -> int | None:
         """Submit a host uint8 [m] syndrome; returns its ticket, or None when

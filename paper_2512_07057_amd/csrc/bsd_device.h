@@ -1234,8 +1234,9 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   const int tid = threadIdx.x;
   if (a.stream && tid == 0) {
     // Serving: the last workgroup to begin tells the host that all are resident.
+    // (the count runs on over relaunches of the same decoder)
     const uint32_t k = __hip_atomic_fetch_add(&a.st->started_wgs, 1u, __ATOMIC_RELAXED, AGENT) + 1u;
-    if (k == gridDim.x) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (k % gridDim.x == 0) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
@@ -1388,6 +1389,9 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
     }
   }
   if (tid == 0) {
+    // The spare context goes back: a serving decoder that ends when idle is
+    // started again later and needs every context.
+    if (spare >= 0) ring_push(&a.st->ctxq, a.ctx_ring, (uint32_t)spare);
     __hip_atomic_fetch_add(&a.st->runs, nruns, __ATOMIC_RELAXED, AGENT);
     __hip_atomic_fetch_add(&a.st->iterations, niters, __ATOMIC_RELAXED, AGENT);
   }

@@ -1430,7 +1430,7 @@ bsd_status bsd_code_autotune(bsd_code c, const bsd_params* p, int64_t shots, con
 
 namespace {
 
-constexpr uint32_t kDecoderIdleTicks = 2000000000u;  // 20 s at 100 MHz
+constexpr uint32_t kDecoderIdleTicks = 2000000000u;  // default idle limit: 20 s at 100 MHz
 
 struct ServeQ {
   bsd_code code = nullptr;
@@ -1448,6 +1448,8 @@ struct ServeQ {
   unsigned long long* d_pub = nullptr;
   uint64_t next = 0;                   // tickets issued
   std::vector<int64_t> row_ticket;     // ticket holding each row, -1 if free
+  BatchArgs args{};                    // of the decoder's launches
+  int64_t launches = 0;                // the first and every relaunch after an idle exit
 };
 
 template <class T>
@@ -1511,11 +1513,41 @@ bsd_status server_stop(bsd_server s) {
   return BSD_OK;
 }
 
-bool server_alive(bsd_server s) {
-  if (!s->launched) return false;
-  for (int i = 0; i < s->n; ++i)
-    if (hipStreamQuery(s->q[i].stream) != hipErrorNotReady) return false;
-  return true;
+bool decoder_running(const ServeQ& q) { return hipStreamQuery(q.stream) == hipErrorNotReady; }
+
+// Launch (or relaunch) one decoder and wait until every workgroup runs.
+bsd_status launch_decoder(ServeQ& q, int index) {
+  __atomic_store_n(q.started, 0u, __ATOMIC_RELEASE);
+  hipError_t he = launch_batched(q.args, q.grid, q.code->block, q.code->cpt, q.code->pw,
+                                 q.code->lds, q.stream);
+  if (he != hipSuccess) return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
+  ++q.launches;
+  const double t0 = now_us();
+  while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
+    if (now_us() - t0 > 5e6)
+      return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every workgroup "
+                  "running within 5 s; more hardware queues (GPU_MAX_HW_QUEUES) or fewer "
+                  "workgroups may be needed", index, q.grid);
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+  return BSD_OK;
+}
+
+// A decoder that ended after its idle limit is started again: requests
+// published since are claimed by the new launch (its state, rings and
+// contexts carry over; every context was returned when the workgroups ended).
+bsd_status ensure_decoder(bsd_server s, int code) {
+  if (!s->launched) return fail(BSD_EDEVICE, "serving kernels have stopped");
+  ServeQ& q = s->q[code];
+  if (decoder_running(q)) return BSD_OK;
+  return launch_decoder(q, code);
+}
+
+// Hardware queues HIP gives this process (GPU_MAX_HW_QUEUES, default 4).
+int hw_queues() {
+  const char* e = getenv("GPU_MAX_HW_QUEUES");
+  const int v = e ? atoi(e) : 0;
+  return v > 0 ? v : 4;
 }
 
 }  // namespace
@@ -1524,11 +1556,28 @@ extern "C" {
 
 bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
                              const int32_t* grid_blocks, int64_t ring_bytes, bsd_server* out) {
+  bsd_server_opts o{};
+  o.ring_bytes = ring_bytes;
+  return bsd_server_create_ex(ncodes, codes, params, grid_blocks, &o, out);
+}
+
+bsd_status bsd_server_create_ex(int32_t ncodes, const bsd_code* codes, const bsd_params* params,
+                                const int32_t* grid_blocks, const bsd_server_opts* opts,
+                                bsd_server* out) {
   if (!out) return fail(BSD_EINVAL, "out is NULL");
   *out = nullptr;
   if (ncodes < 1 || ncodes > kMaxServe || !codes || !params)
     return fail(BSD_EINVAL, "need 1..%d codes and their params", kMaxServe);
+  const int64_t ring_bytes = opts ? opts->ring_bytes : 0;
+  const int64_t idle_ms = opts ? opts->idle_ms : 0;
   if (ring_bytes < 0) return fail(BSD_EINVAL, "ring_bytes must be >= 0");
+  if (idle_ms < 0 || idle_ms > 40000) return fail(BSD_EINVAL, "idle_ms must be in [0, 40000]");
+  // Each decoder is a persistent kernel on a stream of its own; they must all
+  // run at once, which needs a hardware queue each.
+  if (ncodes > hw_queues())
+    return fail(BSD_EINVAL, "serving %d codes needs %d hardware queues, and this process has %d "
+                "(set GPU_MAX_HW_QUEUES before HIP initialises)", ncodes, ncodes, hw_queues());
+  const uint32_t idle_ticks = idle_ms > 0 ? (uint32_t)(idle_ms * 100000) : kDecoderIdleTicks;
   int dev = 0;
   HIP_OR_FAIL(hipGetDevice(&dev));
   for (int i = 0; i < ncodes; ++i) {
@@ -1622,7 +1671,7 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
     a.pub_host = q.d_pub;
     a.stop_host = s->d_stop;
     a.started = q.d_started;
-    a.idle_limit = kDecoderIdleTicks;
+    a.idle_limit = idle_ticks;
     a.shots = 0;
     he = launch_batch_reset(a, q.stream);
     if (he == hipSuccess) he = hipStreamSynchronize(q.stream);
@@ -1643,23 +1692,12 @@ bsd_status bsd_server_create(int32_t ncodes, const bsd_code* codes, const bsd_pa
   s->launched = true;
   for (int i : order) {
     ServeQ& q = s->q[i];
-    hipError_t he = launch_batched(args[i], q.grid, q.code->block, q.code->cpt, q.code->pw,
-                                   q.code->lds, q.stream);
-    if (he != hipSuccess) {
-      (void)server_stop(s);
-      server_free(s);
-      return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
-    }
-    const double t0 = now_us();
-    while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
-      if (now_us() - t0 > 5e6) {
-        const bsd_status st = server_stop(s);
-        if (st == BSD_OK) server_free(s);
-        return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every workgroup "
-                    "running within 5 s; more hardware queues (GPU_MAX_HW_QUEUES) or fewer "
-                    "workgroups may be needed", i, q.grid);
-      }
-      std::this_thread::sleep_for(std::chrono::microseconds(100));
+    q.args = args[i];
+    const bsd_status st = launch_decoder(q, i);
+    if (st != BSD_OK) {
+      const std::string msg = g_err;
+      if (server_stop(s) == BSD_OK) server_free(s);
+      return fail(st, "%s", msg.c_str());
     }
   }
   *out = s;
@@ -1673,7 +1711,7 @@ bsd_status bsd_server_submit(bsd_server s, int32_t code, const uint8_t* syndrome
   const uint64_t t = q.next;
   const uint32_t row = (uint32_t)(t & (q.rows - 1));
   if (q.row_ticket[row] >= 0) return fail(BSD_EBUSY, "ring of code %d is full", code);
-  if (!server_alive(s)) return fail(BSD_EDEVICE, "serving kernels have stopped");
+  if (!s->launched) return fail(BSD_EDEVICE, "serving kernels have stopped");
   for (int i = 0; i < g.m; ++i)
     if (syndrome[i] > 1) return fail(BSD_EINVAL, "syndrome bytes must be 0 or 1");
   std::memcpy(q.syn + (size_t)row * g.m, syndrome, g.m);
@@ -1681,7 +1719,9 @@ bsd_status bsd_server_submit(bsd_server s, int32_t code, const uint8_t* syndrome
   q.next = t + 1;
   __atomic_store_n(q.pub, (unsigned long long)(t + 1), __ATOMIC_RELEASE);
   if (ticket) *ticket = (int64_t)t;
-  return BSD_OK;
+  // Published first, then checked: a decoder that ends after this check
+  // is started again by the poll that finds the request unanswered.
+  return ensure_decoder(s, code);
 }
 
 bsd_status bsd_server_poll(bsd_server s, int32_t code, int64_t ticket, uint8_t* corrections,
@@ -1692,7 +1732,8 @@ bsd_status bsd_server_poll(bsd_server s, int32_t code, int64_t ticket, uint8_t* 
   const uint32_t row = (uint32_t)((uint64_t)ticket & (q.rows - 1));
   if (q.row_ticket[row] != ticket) return fail(BSD_EINVAL, "ticket %lld is not in flight", (long long)ticket);
   if (__atomic_load_n(&q.done[row], __ATOMIC_ACQUIRE) != (uint32_t)(ticket + 1)) {
-    if (!server_alive(s)) return fail(BSD_EDEVICE, "serving kernels have stopped");
+    const bsd_status st = ensure_decoder(s, code);
+    if (st != BSD_OK) return st;
     return BSD_EBUSY;  // not finished yet (no error message)
   }
   if (corrections) std::memcpy(corrections, q.corr + (size_t)row * g.n, g.n);
@@ -1700,6 +1741,13 @@ bsd_status bsd_server_poll(bsd_server s, int32_t code, int64_t ticket, uint8_t* 
   if (converged) *converged = q.conv[row];
   if (device_ticks) *device_ticks = q.lat[row];
   q.row_ticket[row] = -1;
+  return BSD_OK;
+}
+
+bsd_status bsd_server_info(bsd_server s, int32_t code, int32_t* running, int64_t* launches) {
+  if (!s || code < 0 || code >= s->n) return fail(BSD_EINVAL, "bad server or code");
+  if (running) *running = s->launched && decoder_running(s->q[code]) ? 1 : 0;
+  if (launches) *launches = s->q[code].launches;
   return BSD_OK;
 }
 

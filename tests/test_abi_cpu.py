@@ -85,3 +85,16 @@ def test_decode_rejects_bad_params_before_device_work():
     prm = bsd.make_params(10, 0, 20, 8)
     rc = lib.bsd_decode(None, C.byref(prm), 1, None, None, None, None, None)
     assert rc == bsd.BSD_EINVAL and "code is NULL" in lib.bsd_last_error().decode()
+
+
+def test_server_needs_a_hardware_queue_per_code(monkeypatch):
+    """bsd_server_create_ex refuses more codes than the process has hardware
+    queues (checked before any device call)."""
+    lib = bsd.load()
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", "4")
+    codes = (C.c_void_p * 5)(*[C.c_void_p(16 * (i + 1)) for i in range(5)])
+    prm = (bsd.Params * 5)()
+    out = C.c_void_p()
+    rc = lib.bsd_server_create_ex(5, codes, prm, None, None, C.byref(out))
+    assert rc == bsd.BSD_EINVAL
+    assert b"hardware queues" in lib.bsd_last_error()

@@ -94,3 +94,36 @@ def test_admission_holds_requests_when_ring_full(bsd, setup):
         np.testing.assert_array_equal(r["corrections"], ref["corrections"][t])
         np.testing.assert_array_equal(r["flips"], ref["flips"][t])
         assert r["converged"] == ref["converged"][t]
+
+
+def test_decoders_restart_after_idle(bsd, setup):
+    """Decoders that end after their idle limit (100 ms here) are started
+    again by the next request, six times over; every answer equals the
+    syndrome decoded alone.  A workgroup that ends returns its spare
+    context, so no relaunch loses any (without that the [[144,12,12]]
+    decoder, 32 workgroups over 96 contexts, would stall by the fourth)."""
+    import time
+    codes, params, syns = setup
+    refs = [_alone(codes[i], params[i], syns[i][:60]) for i in range(2)]
+    with bsd.Server(codes[:2], params[:2], idle_ms=100) as srv:
+        for cycle in range(6):
+            tickets = [[srv.submit(i, syns[i][q]) for q in range(60)] for i in range(2)]
+            got = [dict() for _ in range(2)]
+            t0 = time.time()
+            while any(len(got[i]) < 60 for i in range(2)):
+                assert time.time() - t0 < 20, f"cycle {cycle}: requests not answered"
+                for i in range(2):
+                    for q, t in enumerate(tickets[i]):
+                        if q not in got[i]:
+                            r = srv.poll(i, t)
+                            if r is not None:
+                                got[i][q] = r
+            for i in range(2):
+                for q, r in got[i].items():
+                    np.testing.assert_array_equal(r["corrections"], refs[i]["corrections"][q])
+                    assert r["converged"] == refs[i]["converged"][q]
+            time.sleep(0.6)
+            info = [srv.info(i) for i in range(2)]
+            gc.log("cycle", cycle, info)
+            assert not any(x["running"] for x in info), info
+        assert all(srv.info(i)["launches"] == 6 for i in range(2))
