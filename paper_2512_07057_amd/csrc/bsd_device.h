@@ -1232,11 +1232,21 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   load_res<CPT, PW>(a.g, L, R);
   unsigned long long nruns = 0, niters = 0;
   const int tid = threadIdx.x;
-  if (a.stream && tid == 0) {
-    // Serving: the last workgroup to begin tells the host that all are resident.
-    // (the count runs on over relaunches of the same decoder)
-    const uint32_t k = __hip_atomic_fetch_add(&a.st->started_wgs, 1u, __ATOMIC_RELAXED, AGENT) + 1u;
-    if (k % gridDim.x == 0) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (a.stream) {
+    // Serving.  A launch that the host has replaced (it waited behind another
+    // persistent kernel on a shared hardware queue) ends before touching
+    // any state.
+    if (tid == 0)
+      L.misc()[31] = __hip_atomic_load(a.gen_host, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != a.gen;
+    __syncthreads();
+    if (L.misc()[31]) return;
+    if (tid == 0) {
+      __hip_atomic_store(a.begun, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      // The last workgroup to begin tells the host that all are resident
+      // (the count runs on over relaunches of the same decoder).
+      const uint32_t k = __hip_atomic_fetch_add(&a.st->started_wgs, 1u, __ATOMIC_RELAXED, AGENT) + 1u;
+      if (k % gridDim.x == 0) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
   constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
@@ -1389,9 +1399,10 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
     }
   }
   if (tid == 0) {
-    // The spare context goes back: a serving decoder that ends when idle is
-    // started again later and needs every context.
-    if (spare >= 0) ring_push(&a.st->ctxq, a.ctx_ring, (uint32_t)spare);
+    // Serving: the spare context goes back, since a decoder that ends when
+    // idle is started again later and needs every context.  (A batched
+    // call's next launch resets the context queue.)
+    if (a.stream && spare >= 0) ring_push(&a.st->ctxq, a.ctx_ring, (uint32_t)spare);
     __hip_atomic_fetch_add(&a.st->runs, nruns, __ATOMIC_RELAXED, AGENT);
     __hip_atomic_fetch_add(&a.st->iterations, niters, __ATOMIC_RELAXED, AGENT);
   }

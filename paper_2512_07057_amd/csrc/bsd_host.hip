@@ -1441,10 +1441,12 @@ struct ServeQ {
   uint32_t rows = 0;  // ring rows, a power of two
   // Pinned host memory (device views in d_*): syndromes, outputs, flags.
   uint8_t *syn = nullptr, *corr = nullptr, *flips = nullptr, *conv = nullptr;
-  uint32_t *lat = nullptr, *done = nullptr, *started = nullptr;
+  uint32_t *lat = nullptr, *done = nullptr, *started = nullptr, *begun = nullptr, *gen = nullptr;
   unsigned long long* pub = nullptr;
   uint8_t *d_syn = nullptr, *d_corr = nullptr, *d_flips = nullptr, *d_conv = nullptr;
-  uint32_t *d_lat = nullptr, *d_done = nullptr, *d_started = nullptr;
+  uint32_t *d_lat = nullptr, *d_done = nullptr, *d_started = nullptr, *d_begun = nullptr,
+           *d_gen = nullptr;
+  std::vector<hipStream_t> old_streams;  // streams of replaced launches (destroyed with the server)
   unsigned long long* d_pub = nullptr;
   uint64_t next = 0;                   // tickets issued
   std::vector<int64_t> row_ticket;     // ticket holding each row, -1 if free
@@ -1489,8 +1491,11 @@ void server_free(bsd_server s) {
     hipHostFree(q.lat);
     hipHostFree(q.done);
     hipHostFree(q.started);
+    hipHostFree(q.begun);
+    hipHostFree(q.gen);
     hipHostFree(q.pub);
     if (q.stream) hipStreamDestroy(q.stream);
+    for (hipStream_t os : q.old_streams) hipStreamDestroy(os);
     if (q.code) q.code->busy--;
   }
   hipHostFree(s->stop);
@@ -1504,7 +1509,10 @@ bsd_status server_stop(bsd_server s) {
   const double t0 = now_us();
   for (;;) {
     bool all = true;
-    for (int i = 0; i < s->n; ++i) all = all && hipStreamQuery(s->q[i].stream) != hipErrorNotReady;
+    for (int i = 0; i < s->n; ++i) {
+      all = all && hipStreamQuery(s->q[i].stream) != hipErrorNotReady;
+      for (hipStream_t os : s->q[i].old_streams) all = all && hipStreamQuery(os) != hipErrorNotReady;
+    }
     if (all) break;
     if (now_us() - t0 > 60e6) return fail(BSD_EDEVICE, "serving kernels did not stop within 60 s");
     std::this_thread::sleep_for(std::chrono::microseconds(200));
@@ -1516,21 +1524,47 @@ bsd_status server_stop(bsd_server s) {
 bool decoder_running(const ServeQ& q) { return hipStreamQuery(q.stream) == hipErrorNotReady; }
 
 // Launch (or relaunch) one decoder and wait until every workgroup runs.
+// HIP maps streams to a limited set of hardware queues; two decoders whose
+// streams share one run in turn, and a persistent decoder behind another
+// never starts.  A launch none of whose workgroups has begun after a short
+// wait is therefore replaced: the generation moves on (the old launch ends
+// at once whenever it starts) and the decoder is launched on a new stream.
 bsd_status launch_decoder(ServeQ& q, int index) {
-  __atomic_store_n(q.started, 0u, __ATOMIC_RELEASE);
-  hipError_t he = launch_batched(q.args, q.grid, q.code->block, q.code->cpt, q.code->pw,
-                                 q.code->lds, q.stream);
-  if (he != hipSuccess) return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
-  ++q.launches;
-  const double t0 = now_us();
-  while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
-    if (now_us() - t0 > 5e6)
-      return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every workgroup "
-                  "running within 5 s; more hardware queues (GPU_MAX_HW_QUEUES) or fewer "
-                  "workgroups may be needed", index, q.grid);
-    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  constexpr int kAttempts = 6;
+  for (int attempt = 0; attempt < kAttempts; ++attempt) {
+    const uint32_t g = __atomic_load_n(q.gen, __ATOMIC_RELAXED) + 1u;
+    __atomic_store_n(q.begun, 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(q.started, 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(q.gen, g, __ATOMIC_RELEASE);
+    q.args.gen = g;
+    hipError_t he = launch_batched(q.args, q.grid, q.code->block, q.code->cpt, q.code->pw,
+                                   q.code->lds, q.stream);
+    if (he != hipSuccess) return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
+    ++q.launches;
+    const double t0 = now_us();
+    bool begun = false;
+    while (!(begun = __atomic_load_n(q.begun, __ATOMIC_ACQUIRE)) && now_us() - t0 < 250e3)
+      std::this_thread::sleep_for(std::chrono::microseconds(100));
+    if (!begun) {  // queued behind another kernel: a new stream for the next attempt
+      hipStream_t ns = nullptr;
+      he = hipStreamCreateWithFlags(&ns, hipStreamNonBlocking);
+      if (he != hipSuccess) return fail(BSD_EDEVICE, "serving stream: %s", hipGetErrorString(he));
+      q.old_streams.push_back(q.stream);
+      q.stream = ns;
+      continue;
+    }
+    while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
+      if (now_us() - t0 > 5e6)
+        return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every "
+                    "workgroup running within 5 s; fewer workgroups may be needed", index, q.grid);
+      std::this_thread::sleep_for(std::chrono::microseconds(100));
+    }
+    return BSD_OK;
   }
-  return BSD_OK;
+  // (the generation moves on once more, so that no queued launch runs later)
+  __atomic_store_n(q.gen, __atomic_load_n(q.gen, __ATOMIC_RELAXED) + 1u, __ATOMIC_RELEASE);
+  return fail(BSD_EDEVICE, "serving decoder %d did not start on any of %d streams: every "
+              "hardware queue tried was busy with another persistent kernel", index, kAttempts);
 }
 
 // A decoder that ended after its idle limit is started again: requests
@@ -1628,6 +1662,8 @@ bsd_status bsd_server_create_ex(int32_t ncodes, const bsd_code* codes, const bsd
           (e = pinned(&q.lat, &q.d_lat, rows)) != hipSuccess ||
           (e = pinned(&q.done, &q.d_done, rows)) != hipSuccess ||
           (e = pinned(&q.started, &q.d_started, 1)) != hipSuccess ||
+          (e = pinned(&q.begun, &q.d_begun, 1)) != hipSuccess ||
+          (e = pinned(&q.gen, &q.d_gen, 1)) != hipSuccess ||
           (e = pinned(&q.pub, &q.d_pub, 1)) != hipSuccess ||
           (e = hipStreamCreateWithFlags(&q.stream, hipStreamNonBlocking)) != hipSuccess)
         st = fail(BSD_ENOMEM, "serving buffers for code %d: %s", i, hipGetErrorString(e));
@@ -1671,6 +1707,8 @@ bsd_status bsd_server_create_ex(int32_t ncodes, const bsd_code* codes, const bsd
     a.pub_host = q.d_pub;
     a.stop_host = s->d_stop;
     a.started = q.d_started;
+    a.begun = q.d_begun;
+    a.gen_host = q.d_gen;
     a.idle_limit = idle_ticks;
     a.shots = 0;
     he = launch_batch_reset(a, q.stream);

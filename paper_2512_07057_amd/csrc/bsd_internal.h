@@ -147,6 +147,9 @@ struct BatchArgs {
   const uint32_t* stop_host;           // host memory: nonzero ends the kernel
   uint32_t* done_flag;         // per row: low 32 bits of shot + 1 once its outputs are written
   uint32_t* started;           // host memory: set to 1 once every workgroup of the launch runs
+  uint32_t* begun;             // host memory: set to 1 when the launch's first workgroup runs
+  const uint32_t* gen_host;    // host memory: the decoder's current launch generation
+  uint32_t gen;                // this launch's generation (a replaced launch ends at once)
   uint32_t idle_limit;         // also end after this many 100 MHz ticks with nothing to do
   long long shots;
   const uint8_t* syn;
