@@ -358,6 +358,21 @@ bsd_status bsd_unroll_backward(bsd_code code, int32_t elem_bytes, int32_t T, int
                                const void* checkpoints, const void* grad_post, void* grad_lambda,
                                void* grad_alpha, void* workspace, void* stream);
 
+/* As bsd_unroll_backward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument, and no allocation.  The per-shot
+ * partial gradients go to an 8 MiB array the library holds on each device
+ * it runs on, until the process ends: shots * (n + T) * elem_bytes must not
+ * exceed 8 MiB (BSD_EINVAL with the limit otherwise; 6,200 shots of the
+ * [[144,12,12]] graph at T = 25 in double precision).  Calls on one device
+ * share the array: calls that overlap on one device race.  Results equal
+ * bsd_unroll_backward's bit for bit.  Asynchronous on `stream`. */
+bsd_status bsd_unroll_backward_noalloc(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K,
+                                       int64_t shots, const uint8_t* syndromes, const void* lambda,
+                                       const void* alpha, const void* checkpoints,
+                                       const void* grad_post, void* grad_lambda, void* grad_alpha,
+                                       void* stream);
+
 /* Thread-local message describing the last failure in this thread. */
 const char* bsd_last_error(void);
 

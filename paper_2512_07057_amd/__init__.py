@@ -117,6 +117,8 @@ def load():
     lib.bsd_unroll_forward.argtypes = [P, i32, i32, i32, i64, P, P, P, P, P, P]
     lib.bsd_unroll_backward.restype = C.c_int
     lib.bsd_unroll_backward.argtypes = [P, i32, i32, i32, i64, P, P, P, P, P, P, P, P, P]
+    lib.bsd_unroll_backward_noalloc.restype = C.c_int
+    lib.bsd_unroll_backward_noalloc.argtypes = [P, i32, i32, i32, i64, P, P, P, P, P, P, P, P]
     lib.bsd_bp_run.restype = C.c_int
     lib.bsd_bp_run.argtypes = [P, P, i32p, i32, P, i32, C.c_float, i32, P, P, P, i32p, i32p, i32p,
                                C.POINTER(C.c_float), P]

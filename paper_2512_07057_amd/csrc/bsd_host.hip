@@ -1013,6 +1013,20 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   }
   c->s_edgerows = reinterpret_cast<uint4*>(d_ser);
   c->s_edgecol = reinterpret_cast<uint2*>(d_sec);
+  // Unrolled decoder: the CSC pointers, and each row's edges (CSC positions)
+  // in ascending column order.
+  {
+    std::vector<int32_t> re((size_t)nnz);
+    std::vector<int32_t> fill(srp.begin(), srp.end() - 1);
+    for (int j = 0; j < n; ++j)
+      for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) re[fill[h_rowidx[e]]++] = e;
+    if (dev_upload(&c->u_colptr, c->colptr) != hipSuccess || dev_upload(&c->u_rowptr, srp) != hipSuccess ||
+        dev_upload(&c->u_rowedge, re) != hipSuccess) {
+      (void)hipGetLastError();
+      bsd_code_destroy(c);
+      return fail(BSD_ENOMEM, "cannot upload the unrolled decoder's tables");
+    }
+  }
   c->screen_per_cu = screen_blocks_per_cu(m);
   c->d_lam64 = d_l64;
   g.diag_ptr = d_diag;
@@ -1937,19 +1951,6 @@ bsd_status unroll_prepare(bsd_code c, int32_t elem, int32_t T, int32_t K, int64_
   if (T < 0 || T > 4096 || K < 1 || shots < 0 || shots > (int64_t)1 << 31)
     return fail(BSD_EINVAL, "need 0 <= T <= 4096, K >= 1, 0 <= shots < 2^31");
   const DevGraph& g = c->g;
-  if (!c->u_colptr) {
-    std::vector<int32_t> rp(g.m + 1, 0), re(g.nnz);
-    for (int e = 0; e < g.nnz; ++e) rp[c->rowidx[e] + 1]++;
-    for (int i = 0; i < g.m; ++i) rp[i + 1] += rp[i];
-    std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
-    for (int j = 0; j < g.n; ++j)  // ascending column within each row
-      for (int e = c->colptr[j]; e < c->colptr[j + 1]; ++e) re[fill[c->rowidx[e]]++] = e;
-    if (dev_upload(&c->u_colptr, c->colptr) != hipSuccess || dev_upload(&c->u_rowptr, rp) != hipSuccess ||
-        dev_upload(&c->u_rowedge, re) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(BSD_ENOMEM, "cannot upload the unrolled decoder's tables");
-    }
-  }
   UnrollArgs u{};
   u.m = g.m;
   u.n = g.n;
@@ -2030,6 +2031,45 @@ bsd_status bsd_unroll_backward(bsd_code code, int32_t elem_bytes, int32_t T, int
   HIP_OR_FAIL(hipGetDevice(&dev_prev));
   HIP_OR_FAIL(hipSetDevice(code->device));
   const hipError_t e = launch_unroll_backward(a, elem_bytes, (hipStream_t)stream);
+  (void)hipSetDevice(dev_prev);
+  if (e != hipSuccess) return fail(BSD_EDEVICE, "unrolled backward: %s", hipGetErrorString(e));
+  return BSD_OK;
+}
+
+bsd_status bsd_unroll_backward_noalloc(bsd_code code, int32_t elem_bytes, int32_t T, int32_t K,
+                                       int64_t shots, const uint8_t* syndromes, const void* lambda,
+                                       const void* alpha, const void* checkpoints,
+                                       const void* grad_post, void* grad_lambda, void* grad_alpha,
+                                       void* stream) {
+  UnrollArgs a{};
+  bsd_status st = unroll_prepare(code, elem_bytes, T, K, shots, &a);
+  if (st != BSD_OK) return st;
+  const size_t need = (size_t)shots * ((size_t)a.n + (size_t)a.T) * (size_t)elem_bytes;
+  if (need > kNoAllocScratchBytes)
+    return fail(BSD_EINVAL, "needs %zu bytes of scratch for %lld shots; the limit is %zu bytes "
+                "(%lld shots of this graph and T)", need, (long long)shots, kNoAllocScratchBytes,
+                (long long)(kNoAllocScratchBytes / (((size_t)a.n + a.T) * elem_bytes)));
+  if (!grad_lambda || (T > 0 && !grad_alpha)) return fail(BSD_EINVAL, "NULL gradient buffer");
+  if (shots > 0 && (!syndromes || !lambda || (T > 0 && !alpha) || (T > 0 && !checkpoints) ||
+                    !grad_post))
+    return fail(BSD_EINVAL, "NULL buffer");
+  int dev_prev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev_prev));
+  HIP_OR_FAIL(hipSetDevice(code->device));
+  void* ws = nullptr;
+  hipError_t e = noalloc_scratch(code->device, &ws);
+  if (e == hipSuccess) {
+    a.syn = syndromes;
+    a.lam = lambda;
+    a.alpha = alpha;
+    a.ckpt = const_cast<void*>(checkpoints);  // read only by the backward kernels
+    a.gpost = grad_post;
+    a.gl_part = ws;
+    a.ga_part = static_cast<char*>(ws) + (size_t)shots * a.n * elem_bytes;
+    a.grad_lam = grad_lambda;
+    a.grad_alpha = grad_alpha;
+    e = launch_unroll_backward(a, elem_bytes, (hipStream_t)stream);
+  }
   (void)hipSetDevice(dev_prev);
   if (e != hipSuccess) return fail(BSD_EDEVICE, "unrolled backward: %s", hipGetErrorString(e));
   return BSD_OK;

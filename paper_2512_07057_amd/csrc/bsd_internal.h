@@ -285,6 +285,12 @@ struct UnrollArgs {
   void* grad_alpha;               // [T]
   double llr_max;
 };
+// bsd_unroll_backward_noalloc: the partial gradients live in a device array
+// of the library (bsd_unroll.hip); noalloc_scratch gives its address on
+// `device`, which must be current.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void** ptr);
 hipError_t launch_unroll_forward(const UnrollArgs& a, int elem, hipStream_t s);
 hipError_t launch_unroll_backward(const UnrollArgs& a, int elem, hipStream_t s);
 size_t unroll_bwd_lds(const UnrollArgs& a, int elem);

@@ -25,11 +25,20 @@
 // One wave per shot; all state of the shot in LDS.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "bsd_internal.h"
 
 namespace bsd {
 
 namespace {
+
+// Per-shot partial gradients of bsd_unroll_backward_noalloc, in memory the
+// library never allocates: every device the library runs on holds this
+// array until the process ends.  Calls on one device share it, so calls
+// that overlap on one device race; nothing in it needs clearing between
+// calls (the backward kernel writes every partial before the sum reads it).
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
 template <typename F>
 __device__ __forceinline__ F clampv(F x, F lim) {
@@ -266,6 +275,23 @@ hipError_t launch_bwd(const UnrollArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  // The array's name is a host-side stand-in; its device address is looked
+  // up once per device, with that device current (the caller's job).
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 size_t unroll_bwd_lds(const UnrollArgs& a, int elem) {
   return ((size_t)(a.K + 3) * a.nnz + a.n + kUnrollBlock / 64) * elem;
