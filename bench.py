@@ -351,6 +351,7 @@ def main():
         "kernel_ms": kms,
         "kernels": {"k_screen_ms": sms, "k_batched_ms": kms - sms,
                     "screened_shots": int(stats[-1]["screened_shots"]),
+                    "screened_at_t2": int(stats[-1]["screened2_shots"]),
                     "dense_shots": int(shots - stats[-1]["screened_shots"])},
         "work_rate": {"edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
                       "bp_iterations_per_step": iters,

@@ -91,7 +91,14 @@ typedef enum {
    * the columns of its flipped detectors (every other column decides 0 at
    * t = 1) and finishes the shots that converge there; the persistent
    * decoder takes the rest.  Results are identical either way. */
-  BSD_FLAG_NO_SCREEN = 8
+  BSD_FLAG_NO_SCREEN = 8,
+  /* Batched mode: screen iteration 1 only.  By default the screen also
+   * computes iteration 2 of shots that iteration 1 leaves unconverged (when
+   * initial_iters >= 2): only rows that flipped or receive a negative E(1)
+   * can send a negative message at t = 2, every other row's message is
+   * bounded from below, and the columns whose bounded posterior is not
+   * positive get exact messages.  Results are identical either way. */
+  BSD_FLAG_NO_SCREEN2 = 16
 } bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */
@@ -101,8 +108,9 @@ typedef struct {
   int64_t edge_updates;   /* iterations x Tanner edges, summed over runs */
   int64_t deep_shots;     /* shots whose initial BP run did not converge */
   double kernel_ms;       /* device time of the decoding kernels (HIP events) */
-  int64_t screened_shots; /* batched mode: shots finished by the iteration-1 screen */
+  int64_t screened_shots; /* batched mode: shots finished by the screen (iteration 1 or 2) */
   double screen_ms;       /* batched mode: device time of the screen (part of kernel_ms) */
+  int64_t screened2_shots; /* batched mode: of those, shots finished at iteration 2 */
 } bsd_stats;
 
 /* Build a code handle on the current HIP device (Appendix A: the decoding

@@ -23,6 +23,7 @@ FLAG_GRAPH = 1
 FLAG_DENSE_FIRST = 2
 FLAG_ALPHA_SCHEDULE = 4
 FLAG_NO_SCREEN = 8
+FLAG_NO_SCREEN2 = 16
 _lib = None
 
 
@@ -42,7 +43,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("runs", C.c_int64), ("iterations", C.c_int64), ("edge_updates", C.c_int64),
                 ("deep_shots", C.c_int64), ("kernel_ms", C.c_double),
-                ("screened_shots", C.c_int64), ("screen_ms", C.c_double)]
+                ("screened_shots", C.c_int64), ("screen_ms", C.c_double),
+                ("screened2_shots", C.c_int64)]
 
 
 class ServeReport(C.Structure):

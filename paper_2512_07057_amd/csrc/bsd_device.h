@@ -1248,13 +1248,15 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       if (k % gridDim.x == 0) __hip_atomic_store(a.started, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
-  constexpr int kChunk = 8;
   int spare = -1;                 // thread 0 only
   long long cnext = 0, cend = 0;  // thread 0 only: claimed positions [cnext, cend)
   // Thread 0 only: positions to claim, and the shot at a position (the
   // screen's list, written by the previous kernel, or the identity).
   long long nclaim = a.shots;
   if (a.shot_list && tid == 0) nclaim = __hip_atomic_load(&a.st->listed, __ATOMIC_RELAXED, AGENT);
+  // Shots per claim: 8, fewer when there are under 32 per workgroup (a short
+  // list from the screen), so that every workgroup gets some.
+  const long long chunk = nclaim >= 32ll * gridDim.x ? 8 : nclaim >= 4ll * gridDim.x ? 2 : 1;
   auto shot_at = [&](long long q) -> long long { return a.shot_list ? (long long)a.shot_list[q] : q; };
   bool exhausted = false;         // thread 0 only
   int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
@@ -1304,9 +1306,9 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
         if (spare >= 0) {
           if (cnext >= cend) {
             const unsigned long long b = __hip_atomic_fetch_add(
-                &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
+                &a.st->next_shot, (unsigned long long)chunk, __ATOMIC_RELAXED, AGENT);
             cnext = (long long)b;
-            cend = (long long)b + kChunk < nclaim ? (long long)b + kChunk : nclaim;
+            cend = (long long)b + chunk < nclaim ? (long long)b + chunk : nclaim;
             if (cnext >= nclaim) exhausted = true;
           }
           if (cnext < cend) {
@@ -1315,9 +1317,9 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
             item = (uint32_t)spare;
             if (cnext >= cend && !exhausted) {  // claim the next chunk now: its first shot is prefetched
               const unsigned long long b = __hip_atomic_fetch_add(
-                  &a.st->next_shot, (unsigned long long)kChunk, __ATOMIC_RELAXED, AGENT);
+                  &a.st->next_shot, (unsigned long long)chunk, __ATOMIC_RELAXED, AGENT);
               cnext = (long long)b;
-              cend = (long long)b + kChunk < nclaim ? (long long)b + kChunk : nclaim;
+              cend = (long long)b + chunk < nclaim ? (long long)b + chunk : nclaim;
               if (cnext >= nclaim) exhausted = true;
             }
           }

@@ -600,6 +600,36 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
     rt[rank] = make_uint4(xb, yb, (uint32_t)argk | ((uint32_t)par << 8) | ((uint32_t)anyneg << 9), 0u);
     rtab[i] = make_uint4(xb, yb, (uint32_t)ecol[rows[i][argk]], 0u);
   }
+  // Per row, the least E(1) it receives for s = 0 (eq. (2) at t = 1 from the
+  // table's x and y, in the variable phase's single-precision order): the
+  // screen's iteration 2 bounds messages from below with it.  Every prior
+  // LLR is positive wherever the screen runs, so these are positive too.
+  {
+    std::vector<float> e1min((size_t)m, kLlrMax);
+    float d[kMaxDv];
+    for (int j = 0; j < n; ++j) {
+      const int dg = cp[j + 1] - cp[j];
+      for (int e = 0; e < dg; ++e) {
+        const uint4& t = rtab[ri[cp[j] + e]];
+        std::memcpy(&d[e], (int)t.z == j ? &t.y : &t.x, 4);
+      }
+      float pre = lam[j];
+      for (int e = 0; e < dg; ++e) {
+        float x = pre;
+        for (int f = e + 1; f < dg; ++f) x = x + d[f];
+        x = std::fmin(std::fmax(x, -kLlrMax), kLlrMax);
+        float& mn = e1min[ri[cp[j] + e]];
+        mn = std::fmin(mn, x);
+        pre = pre + d[e];
+      }
+    }
+    // (kept 1 % low: a bound stays valid under any difference in the last
+    // bits between this host arithmetic and the device's)
+    for (int i = 0; i < m; ++i) {
+      const float b = 0.99f * e1min[i];
+      std::memcpy(&rtab[i].w, &b, 4);
+    }
+  }
   FiTab* t = new (std::nothrow) FiTab;
   if (!t) return fail(BSD_ENOMEM, "host allocation failed");
   t->alpha = alpha;
@@ -692,9 +722,15 @@ bool use_screen(const bsd_code c, const bsd_params* p, const BatchArgs& a) {
          p->num_results == 1 && c->all_pos && a.fi.enabled;
 }
 
-ScreenArgs screen_args(const bsd_code c, const BatchArgs& a, const FiTab* ft) {
+ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a, const FiTab* ft) {
   const DevGraph& g = c->g;
   ScreenArgs sa{};
+  // Iteration 2 as well when the initial run has one; its scaling is the
+  // schedule's second entry (the last, if shorter) or alpha.
+  sa.t2 = (p->initial_iters >= 2 && !(p->flags & BSD_FLAG_NO_SCREEN2)) ? 1 : 0;
+  sa.alpha2 = (a.alpha_sched && !c->asched.empty())
+                  ? c->asched[std::min<size_t>(2, c->asched.size()) - 1]
+                  : a.alpha;
   sa.m = g.m;
   sa.n = g.n;
   sa.k = g.k;
@@ -757,7 +793,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     }
     a.shot_list = l->d_list;
   }
-  const ScreenArgs sa = screen_args(c, a, ft);
+  const ScreenArgs sa = screen_args(c, p, a, ft);
   const int sgrid = screen_grid(c, shots);
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
@@ -821,6 +857,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
       // (a graph replay is timed as a whole: screen_ms stays 0)
       if (!(p->flags & BSD_FLAG_GRAPH)) (void)hipEventElapsedTime(&sms, l->ev0, l->evs);
       stats->screened_shots = shots - (int64_t)h.listed;
+      stats->screened2_shots = (int64_t)h.done2;
       stats->screen_ms = sms;
     }
   }

@@ -100,7 +100,9 @@ struct BatchState {
   unsigned long long pub;  // shots published
   uint32_t stop;           // nonzero: end the kernel
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
-  int32_t listed;          // shots the iteration-1 screen handed to the dense decoder
+  int32_t listed;          // shots the screen handed to the dense decoder
+  unsigned long long done2;  // shots the screen finished at iteration 2
+  unsigned long long screen_next;  // screen: shots claimed past the statically assigned ones
   uint32_t sticky;         // errors of earlier calls on this workspace, until reported
 };
 
@@ -178,27 +180,32 @@ struct BatchArgs {
   int32_t slots_per_ctx;  // 3 * bw + 1 (the last one keeps the initial run's hard decision)
 };
 
-// Sparse check of iteration 1 of the initial run, one wavefront per shot.
-// From E(0) = Lambda with every Lambda_j > 0, eq. (1) at t = 1 sends each
-// column a message of magnitude x_i (the row's least alpha |Lambda|) or y_i
-// (the second least, to the edge holding the least) with the sign
+// Sparse check of iterations 1 and 2 of the initial run, one wavefront per
+// shot.  From E(0) = Lambda with every Lambda_j > 0, eq. (1) at t = 1 sends
+// each column a message of magnitude x_i (the row's least alpha |Lambda|) or
+// y_i (the second least, to the edge holding the least) with the sign
 // (-1)^{s_i}.  A column with no flipped detector therefore has a positive
 // posterior and decides 0, so the hard decision of iteration 1 is found by
 // summing the posteriors of the columns of flipped detectors only, in the
-// same single-precision order as the dense variable phase.  Shots whose
-// decision satisfies the syndrome are finished here (one iteration, one
-// run); the others are appended to `list` for the dense decoder.
+// same single-precision order as the dense variable phase.  Iteration 2 is
+// found in the same way from the rows that can send a negative message and
+// lower bounds of the others' messages.  Shots whose decision satisfies the
+// syndrome are finished here (one run; one or two iterations); the others
+// are appended to `list` for the dense decoder.
 struct ScreenArgs {
   int32_t m, n, k;
   int32_t words_m;
   int32_t vec;                 // bytes per correction store: 16, 4 or 1 (divides n; aligned)
   int32_t syn8;                // 1: m % 8 == 0 and the syndromes are 8-byte aligned
   int32_t maxdeg_col;          // largest column degree (1..8)
+  int32_t t2;                  // 1: also screen iteration 2 (initial_iters >= 2)
+  float alpha2;                // scaling of eq. (1) at iteration 2
   const int32_t* row_ptr;      // [m + 1] rows (original numbering) in CSR form
   const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
                                //   ascending (0xFFFF unused)
   const uint2* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits
-  const uint4* row_tab;        // [m] x bits, y bits, column of the least |Lambda|, 0
+  const uint4* row_tab;        // [m] x bits, y bits, column of the least |Lambda|, least
+                               //   E(1) of the row for s = 0 (bits)
   const uint64_t* lmask;       // [n]
   long long shots;
   const uint8_t* syn;

@@ -31,6 +31,8 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->stop = 0;
     a.st->poll_token = 0;
     a.st->listed = 0;
+    a.st->done2 = 0;
+    a.st->screen_next = 0;
   }
 }
 

@@ -1,12 +1,15 @@
-"""The sparse screen of iteration 1 in front of the batched decoder.
+"""The sparse screen of iterations 1 and 2 in front of the batched decoder.
 
 At t = 1 from the priors (all positive), only columns of flipped detectors
 can decide 1 (eq. (4)); the screen sums their posteriors in the dense
 variable phase's order and finishes the shots whose decision satisfies the
-syndrome.  Bars: every output, the per-call work counters (runs, iterations,
-deep shots) and the errors equal those of the same call without the screen
-and with iteration 1 computed by eq. (1) in full, on the headline batch and
-on shots that overflow the screen's lists.
+syndrome.  At t = 2 only rows that flipped or receive a negative E(1) send
+negative messages; the screen forms those exactly, bounds the others from
+below, and forms exact messages where the bound does not decide.  Bars:
+every output, the per-call work counters (runs, iterations, deep shots) and
+the errors equal those of the same call with iteration 1 only, without the
+screen, and with iteration 1 computed by eq. (1) in full, on the headline
+batch and on shots that overflow the screen's lists.
 """
 from __future__ import annotations
 
@@ -64,13 +67,13 @@ def test_screen_equals_dense_first_iteration(bsd, wl, hot, shots):
     syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
     gc.log("screen", wl, hot, shots)
     outs = {}
-    for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN),
-                        ("dense", bsd.FLAG_DENSE_FIRST)):
+    for name, flags in (("screen", 0), ("screen1", bsd.FLAG_NO_SCREEN2),
+                        ("no_screen", bsd.FLAG_NO_SCREEN), ("dense", bsd.FLAG_DENSE_FIRST)):
         r = code.decode(syn, _params(bsd, W.params, flags), latency=True)
         torch.cuda.synchronize()
         outs[name] = (_np(r), r["stats"], r["latency_ticks"].cpu().numpy())
         gc.log("  ", name, r["stats"])
-    for name in ("no_screen", "dense"):
+    for name in ("screen1", "no_screen", "dense"):
         _check_same(outs["screen"][0], outs[name][0], name)
         assert outs["screen"][1]["deep_shots"] == outs[name][1]["deep_shots"], name
         if outs["screen"][1]["deep_shots"] == 0:
@@ -80,6 +83,33 @@ def test_screen_equals_dense_first_iteration(bsd, wl, hot, shots):
                 assert outs["screen"][1][k] == outs[name][1][k], (name, k)
     lat = outs["screen"][2]
     assert (lat > 0).all()
+    st, st1 = outs["screen"][1], outs["screen1"][1]
+    assert st1["screened2_shots"] == 0 and st["screened2_shots"] <= st["screened_shots"]
+    assert st["screened_shots"] - st["screened2_shots"] == st1["screened_shots"]
+    if wl == "W2" and not hot:
+        # iteration 2 finishes most shots that iteration 1 leaves
+        assert st["screened2_shots"] > 0.8 * (shots - st1["screened_shots"])
+
+
+def test_screen_iteration2_with_schedule(bsd):
+    """Iteration 2 scaled by the schedule's second entry (iteration 1 by the
+    first): equal to the call without the screen."""
+    W = workloads.WORKLOADS["W2"]
+    pr = gc.problem(W.problem_key)
+    code = bsd.Code.from_problem(pr)
+    code.set_alpha_schedule([0.7, 0.55, 0.625])
+    syn = torch.from_numpy(workloads.shots_for(W, shots=20_000)["syndromes"]).cuda()
+    outs = {}
+    for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN)):
+        r = code.decode(syn, _params(bsd, W.params, bsd.FLAG_ALPHA_SCHEDULE | flags))
+        torch.cuda.synchronize()
+        outs[name] = (_np(r), r["stats"])
+        gc.log("  schedule", name, r["stats"])
+    _check_same(outs["screen"][0], outs["no_screen"][0], "schedule")
+    assert outs["screen"][1]["screened2_shots"] > 0
+    if outs["screen"][1]["deep_shots"] == 0:
+        for k in ("runs", "iterations"):
+            assert outs["screen"][1][k] == outs["no_screen"][1][k], k
 
 
 def test_screen_with_unaligned_buffers(bsd):
