@@ -93,7 +93,8 @@ struct FiTab {
   float alpha = 0.f;
   uint4* d_rows = nullptr;
   uint32_t* d_negbits = nullptr;
-  uint4* d_rowtab = nullptr;
+  float* d_e1min = nullptr;    // screen: least zero-syndrome E(1) per row (lowered 1 %)
+  float* d_pairmag = nullptr;  // screen: per CSR pair, the column's t = 1 magnitudes (8 slots)
   FirstIter fi{};
 };
 
@@ -125,7 +126,7 @@ struct bsd_code_s {
   int32_t* s_rowptr = nullptr;
   uint4* s_edgerows = nullptr;
   uint2* s_edgecol = nullptr;
-  int screen_per_cu = 1;
+  int screen_per_cu = 1, screen2_per_cu = 1;
   int maxdeg_col = 1;
   // Batched decoding: one lane per stream the handle has been used on.
   std::vector<Lane*> lanes;
@@ -246,7 +247,8 @@ bsd_status ensure_batched(bsd_code c, Lane* l, int bw, int num_results) {
 void fitab_free(FiTab* t) {
   hipFree(t->d_rows);
   hipFree(t->d_negbits);
-  hipFree(t->d_rowtab);
+  hipFree(t->d_e1min);
+  hipFree(t->d_pairmag);
   delete t;
 }
 
@@ -573,6 +575,7 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
   std::vector<std::vector<int>> rows(m);
   for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);  // ascending column = diagonal order
   std::vector<uint4> rt((size_t)m), rtab((size_t)m, make_uint4(0u, 0u, 0xFFFFFFFFu, 0u));
+  std::vector<float> t_e1min, t_pairmag;
   std::vector<uint32_t> neg((size_t)g.nnz_pad / 32 + 1, 0u);
   for (int i = 0; i < m; ++i) {
     float m1 = kLlrMax, m2 = kLlrMax;
@@ -625,15 +628,32 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
     }
     // (kept 1 % low: a bound stays valid under any difference in the last
     // bits between this host arithmetic and the device's)
-    for (int i = 0; i < m; ++i) {
-      const float b = 0.99f * e1min[i];
-      std::memcpy(&rtab[i].w, &b, 4);
-    }
+    for (int i = 0; i < m; ++i) e1min[i] = 0.99f * e1min[i];
+    t_e1min.swap(e1min);
+  }
+  // Per (row, column) pair in CSR order (rows ascending, then columns): the
+  // magnitudes of the t = 1 messages on the column's edges, in CSC order --
+  // what the screen sums for the column, without a per-row lookup.
+  {
+    std::vector<int32_t> rp((size_t)m + 1, 0);
+    for (int e = 0; e < nnz; ++e) rp[ri[e] + 1]++;
+    for (int i = 0; i < m; ++i) rp[i + 1] += rp[i];
+    std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+    t_pairmag.assign((size_t)nnz * 8, 0.f);
+    for (int j = 0; j < n; ++j)
+      for (int e = cp[j]; e < cp[j + 1]; ++e) {
+        const size_t q = (size_t)fill[ri[e]]++;
+        for (int f = cp[j]; f < cp[j + 1]; ++f) {
+          const uint4& t = rtab[ri[f]];
+          std::memcpy(&t_pairmag[q * 8 + (f - cp[j])], (int)t.z == j ? &t.y : &t.x, 4);
+        }
+      }
   }
   FiTab* t = new (std::nothrow) FiTab;
   if (!t) return fail(BSD_ENOMEM, "host allocation failed");
   t->alpha = alpha;
-  if (dev_upload(&t->d_rows, rt) != hipSuccess || dev_upload(&t->d_rowtab, rtab) != hipSuccess ||
+  if (dev_upload(&t->d_rows, rt) != hipSuccess || dev_upload(&t->d_e1min, t_e1min) != hipSuccess ||
+      dev_upload(&t->d_pairmag, t_pairmag) != hipSuccess ||
       dev_upload(&t->d_negbits, neg) != hipSuccess) {
     (void)hipGetLastError();
     fitab_free(t);
@@ -742,7 +762,8 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   sa.row_ptr = c->s_rowptr;
   sa.edge_rows = c->s_edgerows;
   sa.edge_col = c->s_edgecol;
-  sa.row_tab = ft ? ft->d_rowtab : nullptr;
+  sa.edge_mag = ft ? reinterpret_cast<const float4*>(ft->d_pairmag) : nullptr;
+  sa.row_e1min = ft ? ft->d_e1min : nullptr;
   sa.lmask = g.lmask;
   sa.shots = a.shots;
   sa.syn = a.syn;
@@ -752,14 +773,18 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   sa.lat = a.lat;
   sa.st = a.st;
   sa.list = const_cast<int32_t*>(a.shot_list);
+  sa.list2 = sa.list ? sa.list + a.shots : nullptr;
   return sa;
 }
 
-// Screen grid: the workgroups that fit on the device at once (each holds the
-// row tables in LDS), fewer for small batches; each wave strides over shots.
-int screen_grid(const bsd_code c, int64_t shots) {
-  const int64_t want = (shots + kScreenBlock / 64 - 1) / (kScreenBlock / 64);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)c->screen_per_cu * c->ncu));
+// Screen grids: the workgroups of each kernel that fit on the device at
+// once (each holds the row tables in LDS), fewer for small batches; each
+// wave takes shots until none are left.
+int screen_grid(const bsd_code c, int64_t shots, int which) {
+  const int waves = (which == 1 ? kScreenBlock : kScreen2Block) / 64;
+  const int64_t want = (shots + waves - 1) / waves;
+  const int per_cu = which == 1 ? c->screen_per_cu : c->screen2_per_cu;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)per_cu * c->ncu));
 }
 
 // One batched call on lane l (its mutex and the configuration lock held).
@@ -784,7 +809,8 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
       hipFree(l->d_list);
       l->d_list = nullptr;
       l->list_cap = 0;
-      if (hipMalloc((void**)&l->d_list, (size_t)shots * 4) != hipSuccess) {
+      // the dense decoder's list, then the iteration-2 screen's
+      if (hipMalloc((void**)&l->d_list, (size_t)shots * 8) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BSD_ENOMEM, "cannot allocate the screen's shot list (%lld shots)", (long long)shots);
       }
@@ -794,7 +820,8 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     a.shot_list = l->d_list;
   }
   const ScreenArgs sa = screen_args(c, p, a, ft);
-  const int sgrid = screen_grid(c, shots);
+  const int sgrid = screen_grid(c, shots, 1);
+  const int sgrid2 = screen_grid(c, shots, 2);
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
     std::vector<char> key(sizeof a + 3 * sizeof(int));
@@ -806,7 +833,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
       if (!l->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&l->cap_stream, hipStreamNonBlocking));
       HIP_OR_FAIL(hipStreamBeginCapture(l->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t e1 = launch_batch_reset(a, l->cap_stream);
-      if (e1 == hipSuccess && screen) e1 = launch_screen(sa, sgrid, l->cap_stream);
+      if (e1 == hipSuccess && screen) e1 = launch_screen(sa, sgrid, sgrid2, l->cap_stream);
       hipError_t e2 = launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, l->cap_stream);
       hipGraph_t gr = nullptr;
       hipError_t e3 = hipStreamEndCapture(l->cap_stream, &gr);
@@ -824,7 +851,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
   } else {
     HIP_OR_FAIL(launch_batch_reset(a, s));
     HIP_OR_FAIL(hipEventRecord(l->ev0, s));
-    if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, s));
+    if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, sgrid2, s));
     HIP_OR_FAIL(hipEventRecord(l->evs, s));
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
     HIP_OR_FAIL(hipEventRecord(l->ev1, s));
@@ -1064,7 +1091,8 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
       return fail(BSD_ENOMEM, "cannot upload the unrolled decoder's tables");
     }
   }
-  c->screen_per_cu = screen_blocks_per_cu(m);
+  c->screen_per_cu = screen_blocks_per_cu(m, 1);
+  c->screen2_per_cu = screen_blocks_per_cu(m, 2);
   c->d_lam64 = d_l64;
   g.diag_ptr = d_diag;
   g.row_of_rank = d_ror;

@@ -102,7 +102,9 @@ struct BatchState {
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
   int32_t listed;          // shots the screen handed to the dense decoder
   unsigned long long done2;  // shots the screen finished at iteration 2
-  unsigned long long screen_next;  // screen: shots claimed past the statically assigned ones
+  unsigned long long screen_next;   // iteration-1 screen: shots claimed past the static ones
+  unsigned long long screen2_next;  // iteration-2 screen: list positions claimed
+  int32_t listed2;                  // shots the iteration-1 screen handed to the iteration-2 screen
   uint32_t sticky;         // errors of earlier calls on this workspace, until reported
 };
 
@@ -204,8 +206,10 @@ struct ScreenArgs {
   const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
                                //   ascending (0xFFFF unused)
   const uint2* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits
-  const uint4* row_tab;        // [m] x bits, y bits, column of the least |Lambda|, least
-                               //   E(1) of the row for s = 0 (bits)
+  const float4* edge_mag;      // [2 nnz] CSR order: the magnitudes of eq. (1) at t = 1 on the
+                               //   edge's column's edges (x_i, or y_i on the edge of the row's
+                               //   least |Lambda|), in the order of edge_rows, 0 unused
+  const float* row_e1min;      // [m] least E(1) the row receives for s = 0 (a lower bound)
   const uint64_t* lmask;       // [n]
   long long shots;
   const uint8_t* syn;
@@ -213,15 +217,20 @@ struct ScreenArgs {
   uint8_t* flips;
   uint8_t* conv;
   uint32_t* lat;               // or NULL
-  BatchState* st;              // error, done, runs, iterations, listed
-  int32_t* list;               // [shots]
+  BatchState* st;              // error, done, runs, iterations, listed, listed2
+  int32_t* list;               // [shots] shots for the dense decoder
+  int32_t* list2;              // [shots] shots for the iteration-2 screen
 };
-constexpr int kScreenBlock = 512;        // eight shots in flight per workgroup
+constexpr int kScreenBlock = 512;        // iteration 1: eight shots in flight per workgroup
+constexpr int kScreen1MinWaves = 4;      // iteration 1: waves per SIMD the registers must allow
+constexpr int kScreen2Block = 512;       // iteration 2
+constexpr int kScreen2MinWaves = 4;      // iteration 2: waves per SIMD the registers must allow
 constexpr int kScreenMaxFlipped = 64;    // more flipped detectors: dense decoder
 constexpr int kScreenMaxCand = 2048;     // more (detector, column) pairs: dense decoder
 constexpr int kScreenMaxSet = 64;        // more set decisions: dense decoder
-size_t screen_lds_bytes(int m);
-int screen_blocks_per_cu(int m);
+// Resident workgroups per CU of the iteration-1 (which = 1) or iteration-2
+// (which = 2) screen kernel for m detectors.
+int screen_blocks_per_cu(int m, int which);
 
 // Arguments of a single BP run launched on its own (plain form, bsd_bp_run).
 struct SingleArgs {
@@ -267,7 +276,8 @@ hipError_t launch_single(const SingleArgs& a, int block, int cpt, int pw, size_t
 hipError_t launch_batched(const BatchArgs& a, int grid, int block, int cpt, int pw, size_t lds,
                           hipStream_t s);
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
-hipError_t launch_screen(const ScreenArgs& a, int grid, hipStream_t s);
+// Both screen kernels (the second when a.t2), in stream order.
+hipError_t launch_screen(const ScreenArgs& a, int grid1, int grid2, hipStream_t s);
 
 constexpr int kMaxServe = 8;  // codes one server can hold
 

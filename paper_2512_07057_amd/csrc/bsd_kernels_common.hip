@@ -33,6 +33,8 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->listed = 0;
     a.st->done2 = 0;
     a.st->screen_next = 0;
+    a.st->screen2_next = 0;
+    a.st->listed2 = 0;
   }
 }
 

@@ -1,6 +1,8 @@
 // Sparse screen of the first two iterations of the initial BP run
 // (Appendix A, eqs. (1)-(4) and the stopping rule at t = 1 and t = 2), one
-// wavefront per shot.
+// wavefront per shot, in two kernels: k_screen1 for iteration 1 of every
+// shot, k_screen2 for iteration 2 of the shots that iteration 1 leaves
+// unconverged.
 //
 // Iteration 1.  From E(0) = Lambda with every Lambda_j > 0 every sign in
 // eq. (1) except (-1)^{s_i} is +1, so at t = 1 detector i sends
@@ -17,27 +19,29 @@
 // flipped detectors.  Eq. (1) at t = 2 sends a negative message only from a
 // row that flipped or that receives a negative E(1): the set S2.  Every
 // column outside the neighbourhood of S2 receives non-negative messages and
-// decides 0.  For a column next to S2 the messages of S2 rows are formed
-// exactly (least and second least |E(1)| of the row, sign parity); the
-// message of any other row is non-negative and at least alpha * min(least
-// zero-syndrome E(1) of the row, least non-negative E(1) on the shot's
-// changed columns).  Single-precision addition and multiplication are
-// monotone, so the posterior summed in the dense order with those lower
-// bounds is at most the exact one: when it is positive the column decides
-// 0.  The few columns where it is not (in practice the columns that decide
-// 1) get exact messages from full scans of their remaining rows.
+// decides 0.  For a column next to S2 the magnitude of an S2 row's message
+// follows from the row's least and second least |E(1)| and the column
+// holding the least, and its sign from the parity of the row's negative
+// E(1); the message of any other row is non-negative and at least
+// alpha * min(least zero-syndrome E(1) of the row, least non-negative E(1)
+// on the shot's changed columns).  Single-precision addition and
+// multiplication are monotone, so a posterior summed in the dense order with
+// lower bounds in place of some terms is at most the exact one: when it is
+// positive the column decides 0.  A column is first bounded with every S2
+// message taken negative (no E(1) needed), then with the S2 messages exact,
+// and the few columns left (in practice the columns that decide 1) get exact
+// messages from full scans of their remaining rows.
 //
 // When H e-hat equals the syndrome after iteration 1 or 2 the shot is
 // finished; otherwise (or when one of the lists below overflows) it is
 // appended to the list that the dense persistent decoder takes its shots
 // from.
 //
-// A workgroup keeps the per-row table (x, y, the column of the least
-// |Lambda|, the least zero-syndrome E(1)) and the row pointers in LDS for
-// the whole launch; each wave holds one shot's bit-vectors, row lists and
-// (row, column) pair lists.  Per shot the global reads are its syndrome
-// (prefetched during the previous shot) and, per (row, column) pair, the
-// column, its prior and its rows.
+// A workgroup keeps the row pointers (and for iteration 2 each row's least
+// zero-syndrome E(1)) in LDS for the whole launch; each wave holds one
+// shot's bit-vectors, row lists and (row, column) pair lists.  Per shot the
+// global reads are its syndrome and, per (row, column) pair, the column, its
+// prior, its rows and the magnitudes of their iteration-1 messages.
 #include <hip/hip_runtime.h>
 
 #include "bsd_internal.h"
@@ -47,40 +51,35 @@ namespace bsd {
 namespace {
 
 constexpr int AGENT = __HIP_MEMORY_SCOPE_AGENT;
-constexpr int kWaves = kScreenBlock / 64;
+constexpr int kWaves1 = kScreenBlock / 64;
+constexpr int kWaves2 = kScreen2Block / 64;
 constexpr int kSynRegs = 4;  // 8-byte syndrome loads per lane: m <= 2048
 #ifndef BSD_SCREEN_UNROLL
 #define BSD_SCREEN_UNROLL 4
 #endif
-#ifndef BSD_SCREEN_MIN_WAVES
-#define BSD_SCREEN_MIN_WAVES 4
+#ifndef BSD_S1W
+#define BSD_S1W kScreen1MinWaves
 #endif
-constexpr int kUnroll = BSD_SCREEN_UNROLL;   // pairs per lane in flight at t = 1
 #ifndef BSD_SCREEN_UNROLL2
 #define BSD_SCREEN_UNROLL2 2
 #endif
-constexpr int kUnroll2 = BSD_SCREEN_UNROLL2; // at t = 2
-constexpr int kMaxRows = kScreenMaxFlipped;  // rows of a pair list (flipped rows, S2)
-constexpr int kMaxX = 32;                    // rows scanned for exact decisions at t = 2
-constexpr int kMaxExact = 32;                // columns decided by exact messages at t = 2
-constexpr int kNone = 0xFFFF;                // absent row slot
+constexpr int kUnroll = BSD_SCREEN_UNROLL;    // pairs per lane in flight, iteration 1
+constexpr int kUnroll2 = BSD_SCREEN_UNROLL2;  // iteration 2
+constexpr int kMaxRows = kScreenMaxFlipped;   // rows of a pair list (flipped rows, S2)
+constexpr int kMaxX = 32;                     // S2 rows that did not flip; rows scanned for exact decisions
+constexpr int kMaxExact = 32;                 // columns decided by exact messages at t = 2
+constexpr int kInfo = kMaxRows + kMaxX;       // row info entries: S2 by rank, then scanned rows
+constexpr int kNone = 0xFFFF;                 // absent row slot
 
-struct WaveLds {
+// One shot's iteration 1: syndrome and residual bits, the flipped rows and
+// their (row, column) pairs, the set decisions.
+struct WaveLds1 {
   uint32_t sbits[64];                  // s by row (m <= 2048)
   uint32_t rbits[64];                  // s + H e-hat
-  uint32_t s2bits[64];                 // rows of S2
-  uint32_t xbits[64];                  // S2 rows that did not flip; later rows to scan
   int32_t cst[kMaxRows];               // first CSR position of each listed row
   int32_t coff[kMaxRows];              // index of its first (row, column) pair
-  uint16_t rows[kMaxRows];             // listed rows, ascending: flipped rows, then S2
-  uint16_t xrows[kMaxX];               // S2 rows that did not flip; later rows to scan
+  uint16_t rows[kMaxRows];             // listed rows, ascending: flipped rows (then S2)
   uint16_t fpre[64];                   // flipped rows in earlier words
-  uint16_t s2pre[64];                  // S2 rows in earlier words
-  uint16_t xpre[64];                   // rows of xbits in earlier words
-  uint32_t rm1[kMaxRows + kMaxX];      // per scanned row (S2, then the others): least |E(1)|,
-  uint32_t rm2[kMaxRows + kMaxX];      //   second least,
-  uint32_t rpar[kMaxRows + kMaxX];     //   s_i xor the parity of negative E(1)
-  int32_t xpos[kMaxExact];             // a CSR position of each column decided exactly
   uint8_t cmap[kScreenMaxCand];        // listed row of each (row, column) pair
   int32_t set[kScreenMaxSet];          // columns with e-hat_j = 1
   int32_t nset;
@@ -88,7 +87,26 @@ struct WaveLds {
   int32_t pad[2];
 };
 
+// Iteration 2 adds S2, the rows to scan and per-row message information.
+struct WaveLds2 : WaveLds1 {
+  uint32_t s2bits[64];                 // rows of S2
+  uint32_t xbits[64];                  // S2 rows that did not flip; later rows to scan
+  uint16_t xrows[kMaxX];
+  uint16_t s2pre[64];                  // S2 rows in earlier words
+  uint16_t xpre[64];                   // rows of xbits in earlier words
+  unsigned long long rk1[kInfo];       // per row: least |E(1)| << 32 | its column,
+  uint32_t rm2[kInfo];                 //   second least |E(1)|,
+  uint32_t rpar[kInfo];                //   s_i xor the parity of negative E(1)
+  int32_t xpos[kMaxExact];             // a CSR position of each column decided exactly
+};
+
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Per-workgroup tables: the row pointers, and for iteration 2 the least
+// zero-syndrome E(1) of each row.
+__host__ __device__ constexpr size_t table_bytes(int m, int which) {
+  return align16(4 * (size_t)(m + 1)) + (which == 2 ? align16(4 * (size_t)m) : 0);
+}
 
 // Orders this wave's LDS accesses across lanes (the LDS serves a wave's
 // instructions in order; this keeps the compiler from moving them).
@@ -100,6 +118,14 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint32_t bit_of(const uint32_t* bits, int r) {
   return (bits[r >> 5] >> (r & 31)) & 1u;
+}
+
+// The same for a row slot that may be absent (kNone: 0).  The load is
+// unconditional, so that the loads of a column's slots issue together.
+__device__ __forceinline__ uint32_t bit_at(const uint32_t* bits, int r) {
+  const uint32_t there = r != 0xFFFF ? 1u : 0u;
+  const uint32_t w = bits[(r & 0x7FF) >> 5];  // (kNone reads an unused word)
+  return (w >> (r & 31)) & there;
 }
 
 // Place of row r among the rows set in `bits` (`pre`: set bits in earlier words).
@@ -130,6 +156,13 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
+// Lane 0's 64-bit value in every lane.
+__device__ __forceinline__ unsigned long long bcast64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, 0, 64);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), 0, 64);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ void load_syn_regs(const ScreenArgs& a, long long shot, int lane,
                                               uint2 (&v)[kSynRegs]) {
   const uint2* s8 = reinterpret_cast<const uint2*>(a.syn + shot * a.m);
@@ -143,7 +176,7 @@ __device__ __forceinline__ void load_syn_regs(const ScreenArgs& a, long long sho
 // Syndrome bits into LDS, from registers (8-byte rows) or byte loads;
 // returns nonzero if a byte is neither 0 nor 1.
 __device__ __forceinline__ uint32_t syndrome_bits(const ScreenArgs& a, long long shot,
-                                                  const uint2 (&v)[kSynRegs], WaveLds& W,
+                                                  const uint2 (&v)[kSynRegs], WaveLds1& W,
                                                   int lane) {
   uint32_t bad = 0;
   W.sbits[lane] = 0u;
@@ -193,7 +226,7 @@ __device__ __forceinline__ int list_rows(const uint32_t* bits, int words, uint16
 // and first pair of each row, and the listed row of each pair.  Returns the
 // number of pairs, or -1 when they do not fit.
 __device__ __forceinline__ int list_pairs(const int32_t* rptr, const uint16_t* rows, int nrows,
-                                          WaveLds& W, int lane) {
+                                          WaveLds1& W, int lane) {
   int st = 0, dg = 0;
   if (lane < nrows) {
     const int i = rows[lane];
@@ -213,13 +246,17 @@ __device__ __forceinline__ int list_pairs(const int32_t* rptr, const uint16_t* r
 }
 
 // fn(listed row index, row, CSR position, column's rows, (column, Lambda
-// bits)) for every pair of the listed rows, U pairs per lane in flight.
-template <int U, class Fn>
-__device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds& W,
+// bits), the column's iteration-1 message magnitudes) for every pair of the
+// listed rows, U pairs per lane in flight.  The magnitudes (MAG, 4 per
+// float4, DV of them) are loaded only when asked for.
+template <int U, int DV, bool MAG, class Fn>
+__device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W,
                                           const uint16_t* rows, int np, int lane, Fn fn) {
+  constexpr int NM = MAG ? (DV + 3) / 4 : 1;
   for (int base = 0; base < np; base += 64 * U) {
     uint4 rq[U];
     uint2 jl[U];
+    float4 mg[U][NM];
     int li[U], pos[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -231,27 +268,41 @@ __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds& W,
         pos[u] = W.cst[li[u]] + (c - W.coff[li[u]]);
         rq[u] = a.edge_rows[pos[u]];
         jl[u] = a.edge_col[pos[u]];
+        if constexpr (MAG) {
+#pragma unroll
+          for (int k = 0; k < NM; ++k) mg[u][k] = a.edge_mag[2 * pos[u] + k];
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (li[u] >= 0) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u]);
+      if (li[u] >= 0) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u], mg[u]);
   }
 }
 
-// Eq. (1) at t = 1 on the edges of column j (rows r[e] ascending, kNone when
-// absent): x or y of the row, negative when s_i = 1; 0 on absent slots.
+// Magnitude of slot e of a column's iteration-1 messages.
+template <int NM>
+__device__ __forceinline__ float mag_at(const float4 (&mg)[NM], int e) {
+  const float4 v = mg[e >> 2];
+  return (e & 3) == 0 ? v.x : (e & 3) == 1 ? v.y : (e & 3) == 2 ? v.z : v.w;
+}
+
 template <int DV>
-__device__ __forceinline__ void col_d1(const uint4& rq, int j, const uint4* tab,
-                                       const uint32_t* sbits, int (&r)[DV], float (&d)[DV]) {
+__device__ __forceinline__ void col_rows(const uint4& rq, int (&r)[DV]) {
+#pragma unroll
+  for (int e = 0; e < DV; ++e) r[e] = row_at(rq, e);
+}
+
+// Eq. (1) at t = 1 on the edges of a column (rows r[e] ascending, kNone
+// when absent): the magnitude of the row's message (x, or y on the edge of
+// its least |Lambda|), negative when s_i = 1; 0 on absent slots.
+template <int DV, int NM>
+__device__ __forceinline__ void col_d1(const int (&r)[DV], const float4 (&mg)[NM],
+                                       const uint32_t* sbits, float (&d)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
-    r[e] = row_at(rq, e);
-    const bool there = r[e] != kNone;
-    const uint4 t = tab[there ? r[e] : 0];
-    const uint32_t sb = there ? bit_of(sbits, r[e]) : 0u;
-    const float mag = __uint_as_float((int)t.z == j ? t.y : t.x);
-    d[e] = there ? (sb ? -mag : mag) : 0.f;
+    const float mag = mag_at<NM>(mg, e);
+    d[e] = r[e] != kNone ? (bit_at(sbits, r[e]) ? -mag : mag) : 0.f;
   }
 }
 
@@ -260,7 +311,7 @@ template <int DV>
 __device__ __forceinline__ int first_in(const uint32_t* bits, const int (&r)[DV]) {
   int first = kNone;
 #pragma unroll
-  for (int e = DV - 1; e >= 0; --e) first = (r[e] != kNone && bit_of(bits, r[e])) ? r[e] : first;
+  for (int e = DV - 1; e >= 0; --e) first = bit_at(bits, r[e]) ? r[e] : first;
   return first;
 }
 
@@ -293,65 +344,9 @@ __device__ __forceinline__ void e1_all(float lam, const float (&d)[DV], float (&
   }
 }
 
-// Eq. (1) at t = 2 on the edge holding v of a scanned row: least (m1) and
-// second least (m2) |E(1)| of the row, sign s_i xor the parity of its
-// negative E(1) (sp) xor the sign of v; magnitude alpha * m2 on an edge
-// holding the least, alpha * m1 elsewhere, clamped -- the dense check
-// phase's operations.
-__device__ __forceinline__ float d2_exact(float v, uint32_t m1b, uint32_t m2b, uint32_t sp,
-                                          float alpha) {
-  const float m1 = __uint_as_float(m1b), m2 = __uint_as_float(m2b);
-  const float d1 = fminf(alpha * m1, kLlrMax), d2 = fminf(alpha * m2, kLlrMax);
-  const float mag = fabsf(v) == m1 ? d2 : d1;
-  return ((sp & 1u) ^ (__float_as_uint(v) >> 31)) ? -mag : mag;
-}
-
-// Row info of the listed rows, each at `base` + its rank in (ibits, ipre):
-// the message bound (the check phase's starting least values) and s_i.
-__device__ __forceinline__ void init_row_info(WaveLds& W, const uint16_t* rows, int nrows,
-                                              const uint32_t* ibits, const uint16_t* ipre, int base,
-                                              int lane) {
-  if (lane < nrows) {
-    const int r = rows[lane];
-    const int q = base + rank_of(ibits, ipre, r);
-    W.rm1[q] = W.rm2[q] = __float_as_uint(kLlrMax);
-    W.rpar[q] = bit_of(W.sbits, r);
-  }
-  wave_sync();
-}
-
-// One E(1) of a row into its info q.  Each edge of the row takes part once:
-// an atomic minimum into rm1 returns the previous least, and the larger of
-// the two goes into rm2, so rm2 ends as the least of all values but one copy
-// of the row minimum.  Magnitudes compare as unsigned integers.
-__device__ __forceinline__ void row_info_add(WaveLds& W, int q, float v) {
-  const uint32_t av = __float_as_uint(v) & 0x7FFFFFFFu;
-  const uint32_t old = atomicMin(&W.rm1[q], av);
-  atomicMin(&W.rm2[q], old > av ? old : av);
-  if (__float_as_uint(v) >> 31) atomicXor(&W.rpar[q], 1u);
-}
-
-// Least and second least |E(1)| and the sign parity of the listed rows, E(1)
-// formed exactly on every edge; info at `base` + rank in (ibits, ipre).
-template <int DV>
-__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds& W, const uint4* tab,
-                                          const uint16_t* rows, int np, const uint32_t* ibits,
-                                          const uint16_t* ipre, int base, int lane) {
-  for_pairs<kUnroll2>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq, const uint2& jl) {
-    int r[DV];
-    float d[DV];
-    col_d1<DV>(rq, (int)jl.x, tab, W.sbits, r, d);
-    int es = 0;
-#pragma unroll
-    for (int e = 0; e < DV; ++e) es = r[e] == i ? e : es;
-    row_info_add(W, base + rank_of(ibits, ipre, i), e1_at<DV>(__uint_as_float(jl.y), d, es));
-  });
-  wave_sync();
-}
-
 // Adds column j to e-hat: its detectors join s + H e-hat.
 template <int DV>
-__device__ __forceinline__ void set_column(WaveLds& W, int j, const int (&r)[DV]) {
+__device__ __forceinline__ void set_column(WaveLds1& W, int j, const int (&r)[DV]) {
   const int q = atomicAdd(&W.nset, 1);
   if (q < kScreenMaxSet) W.set[q] = j;
 #pragma unroll
@@ -359,22 +354,102 @@ __device__ __forceinline__ void set_column(WaveLds& W, int j, const int (&r)[DV]
     if (r[e] != kNone) atomicXor(&W.rbits[r[e] >> 5], 1u << (r[e] & 31));
 }
 
-// Eq. (1) at t = 2 on slot e of a column next to S2: exact for S2 rows and
-// for scanned rows (rank in `xb` / `xp`, info from index kMaxRows), else the
-// lower bound `lb` of the row's message; `exact` is cleared when a bound is used.
+// Per listed row, entry `base` + its rank in (ibits, ipre) of the row info:
+// the message bound (the check phase's starting least values) and s_i.
+__device__ __forceinline__ void init_row_info(WaveLds2& W, const uint16_t* rows, int nrows,
+                                              const uint32_t* ibits, const uint16_t* ipre, int base,
+                                              int lane) {
+  if (lane < nrows) {
+    const int r = rows[lane];
+    const int q = base + rank_of(ibits, ipre, r);
+    W.rk1[q] = ((unsigned long long)__float_as_uint(kLlrMax) << 32) | 0xFFFFFFFFull;
+    W.rm2[q] = __float_as_uint(kLlrMax);
+    W.rpar[q] = bit_of(W.sbits, r);
+  }
+  wave_sync();
+}
+
+// One E(1) (held by column j) of a row into its info q.  Each edge of the
+// row takes part once: an atomic minimum of (|v|, j) into rk1 returns the
+// previous least, and the larger magnitude of the two goes into rm2, so rm2
+// ends as the least of all magnitudes but one copy of the row minimum.
+// Magnitudes compare as unsigned integers.
+__device__ __forceinline__ void row_info_add(WaveLds2& W, int q, float v, int j) {
+  const uint32_t av = __float_as_uint(v) & 0x7FFFFFFFu;
+  const unsigned long long old = atomicMin(&W.rk1[q], ((unsigned long long)av << 32) | (uint32_t)j);
+  const uint32_t oav = (uint32_t)(old >> 32);
+  atomicMin(&W.rm2[q], oav > av ? oav : av);
+  if (__float_as_uint(v) >> 31) atomicXor(&W.rpar[q], 1u);
+}
+
+// Least and second least |E(1)| and the sign parity of the listed rows, E(1)
+// formed exactly on every edge; info at `base` + rank in (ibits, ipre).
 template <int DV>
-__device__ __forceinline__ float d2_term(const WaveLds& W, const uint4* tab, int r, float v,
-                                         float alpha, float gdmin, bool scanned, bool& exact) {
-  if (bit_of(W.s2bits, r)) {
-    const int q = rank_of(W.s2bits, W.s2pre, r);
-    return d2_exact(v, W.rm1[q], W.rm2[q], W.rpar[q], alpha);
+__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W,
+                                          const uint16_t* rows, int np, const uint32_t* ibits,
+                                          const uint16_t* ipre, int base, int lane) {
+  constexpr int NM = (DV + 3) / 4;
+  for_pairs<kUnroll2, DV, true>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq,
+                                                          const uint2& jl, const float4 (&mg)[NM]) {
+    int r[DV];
+    float d[DV];
+    col_rows<DV>(rq, r);
+    col_d1<DV, NM>(r, mg, W.sbits, d);
+    int es = 0;
+#pragma unroll
+    for (int e = 0; e < DV; ++e) es = r[e] == i ? e : es;
+    row_info_add(W, base + rank_of(ibits, ipre, i), e1_at<DV>(__uint_as_float(jl.y), d, es),
+                 (int)jl.x);
+  });
+  wave_sync();
+}
+
+// Magnitude of eq. (1) at t = 2 that a scanned row (info q) sends to column
+// j: alpha * second least |E(1)| to the column holding the least, alpha *
+// least to the others, clamped.  (When another column ties for the least,
+// both are equal.)
+__device__ __forceinline__ float d2_mag(const WaveLds2& W, int q, int j, float alpha) {
+  const unsigned long long k1 = W.rk1[q];
+  const float m = (int)(uint32_t)k1 == j ? __uint_as_float(W.rm2[q])
+                                         : __uint_as_float((uint32_t)(k1 >> 32));
+  return fminf(alpha * m, kLlrMax);
+}
+
+// Info index of row r (not kNone) for eq. (1) at t = 2, or -1 when the row
+// is neither in S2 nor (with `scanned`) among the scanned rows.  The loads
+// do not depend on the tests.
+__device__ __forceinline__ int info_of(const WaveLds2& W, int r, bool scanned) {
+  const uint32_t bit = 1u << (r & 31), below = bit - 1u;
+  const uint32_t w = W.s2bits[r >> 5];
+  const int q = (int)W.s2pre[r >> 5] + __builtin_popcount(w & below);
+  if (!scanned) return (w & bit) ? q : -1;
+  const uint32_t xw = W.xbits[r >> 5];
+  const int qx = kMaxRows + (int)W.xpre[r >> 5] + __builtin_popcount(xw & below);
+  return (w & bit) ? q : (xw & bit) ? qx : -1;
+}
+
+// Lower bound of the message a row outside S2 sends at t = 2.
+__device__ __forceinline__ float d2_lb(const float* e1min, int r, float alpha, float gdmin) {
+  return fminf(alpha * fminf(e1min[r], gdmin), kLlrMax);
+}
+
+// Per slot of a column next to S2: the row's info index (-1 outside S2 and
+// for absent slots), the magnitude of its t = 2 message to column j (S2
+// rows) or the lower bound of it (other rows).
+template <int DV>
+__device__ __forceinline__ void d2_slots(const WaveLds2& W, const float* e1min, const int (&r)[DV],
+                                         int j, float alpha, float gdmin, bool scanned,
+                                         int (&q)[DV], float (&mag)[DV]) {
+#pragma unroll
+  for (int e = 0; e < DV; ++e) {
+    const bool there = r[e] != kNone;
+    const int rs = there ? r[e] : 0;
+    const int qe = info_of(W, rs, scanned);
+    q[e] = there ? qe : -1;
+    const float lb = d2_lb(e1min, rs, alpha, gdmin);
+    const float m = d2_mag(W, qe >= 0 ? qe : 0, j, alpha);
+    mag[e] = qe >= 0 ? m : lb;
   }
-  if (scanned) {
-    const int q = kMaxRows + rank_of(W.xbits, W.xpre, r);
-    return d2_exact(v, W.rm1[q], W.rm2[q], W.rpar[q], alpha);
-  }
-  exact = false;
-  return fminf(alpha * fminf(__uint_as_float(tab[r].w), gdmin), kLlrMax);
 }
 
 // Iteration 2 of a shot whose iteration 1 did not converge (W.rows holds its
@@ -382,7 +457,7 @@ __device__ __forceinline__ float d2_term(const WaveLds& W, const uint4* tab, int
 // e-hat(2) in W.set and s + H e-hat(2) in W.rbits; returns false when a list
 // overflowed (the shot then goes to the dense decoder).
 template <int DV>
-__device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, const int32_t* rptr,
+__device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min, const int32_t* rptr,
                            int nflip, int ncand, int lane) {
   const int words = a.words_m;
   const float alpha = a.alpha2;
@@ -394,11 +469,15 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
   W.s2bits[lane] = W.sbits[lane];
   init_row_info(W, W.rows, nflip, W.sbits, W.fpre, 0, lane);
   float gmin = kLlrMax;
-  for_pairs<kUnroll2>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint2& jl) {
+  constexpr int NM = (DV + 3) / 4;
+  for_pairs<kUnroll2, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
+                                                               const uint2& jl, const float4 (&mg)[NM]) {
     int r[DV];
     float d[DV], E[DV];
-    col_d1<DV>(rq, (int)jl.x, tab, W.sbits, r, d);
+    const int j = (int)jl.x;
+    col_rows<DV>(rq, r);
     if (first_in<DV>(W.sbits, r) != i) return;  // the column's lowest flipped row takes it
+    col_d1<DV, NM>(r, mg, W.sbits, d);
     e1_all<DV>(__uint_as_float(jl.y), d, E);
 #pragma unroll
     for (int e = 0; e < DV; ++e) {
@@ -407,17 +486,18 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
         atomicOr(&W.s2bits[r[e] >> 5], 1u << (r[e] & 31));
       else
         gmin = fminf(gmin, E[e]);
-      if (bit_of(W.sbits, r[e])) row_info_add(W, rank_of(W.sbits, W.fpre, r[e]), E[e]);
+      if (bit_of(W.sbits, r[e])) row_info_add(W, rank_of(W.sbits, W.fpre, r[e]), E[e], j);
     }
   });
   wave_sync();
   const float gdmin = wave_min(gmin);
   // S2, ascending; the flipped rows' info moves to their rank in S2.
   int frow = 0;
-  uint32_t fm1 = 0u, fm2 = 0u, fpar = 0u;
+  unsigned long long fk1 = 0ull;
+  uint32_t fm2 = 0u, fpar = 0u;
   if (lane < nflip) {
     frow = W.rows[lane];
-    fm1 = W.rm1[lane];
+    fk1 = W.rk1[lane];
     fm2 = W.rm2[lane];
     fpar = W.rpar[lane];
   }
@@ -426,7 +506,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
   if (ns2 > kMaxRows) return false;
   if (lane < nflip) {
     const int q = rank_of(W.s2bits, W.s2pre, frow);
-    W.rm1[q] = fm1;
+    W.rk1[q] = fk1;
     W.rm2[q] = fm2;
     W.rpar[q] = fpar;
   }
@@ -438,13 +518,15 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
   init_row_info(W, W.xrows, nn, W.s2bits, W.s2pre, 0, lane);
   const int npn = list_pairs(rptr, W.xrows, nn, W, lane);
   if (npn < 0) return false;
-  scan_rows<DV>(a, W, tab, W.xrows, npn, W.s2bits, W.s2pre, 0, lane);
+  scan_rows<DV>(a, W, W.xrows, npn, W.s2bits, W.s2pre, 0, lane);
   const int np = list_pairs(rptr, W.rows, ns2, W, lane);
   if (np < 0) return false;
 
   // Posteriors (eq. (3)) of the columns next to S2, each taken by its lowest
-  // S2 row.  A column whose bounded posterior is not positive and that used
-  // a bound is listed, and its rows outside S2 are marked for a scan.
+  // S2 row: first with every S2 message taken negative, then with the S2
+  // messages exact.  A column whose bounded posterior is not positive and
+  // that used a bound for a row outside S2 is listed, and those rows are
+  // marked for a scan.
   W.rbits[lane] = W.sbits[lane];
   W.xbits[lane] = 0u;
   if (lane == 0) {
@@ -452,30 +534,45 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
     W.nexact = 0;
   }
   wave_sync();
-  for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint2& jl) {
-    int r[DV];
-    float d[DV], E[DV];
+  for_pairs<kUnroll2, DV, false>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq,
+                                                              const uint2& jl, const float4 (&)[1]) {
+    int r[DV], q[DV];
+    float mag[DV];
     const int j = (int)jl.x;
-    col_d1<DV>(rq, j, tab, W.sbits, r, d);
+    col_rows<DV>(rq, r);
     if (first_in<DV>(W.s2bits, r) != i) return;
     const float lam = __uint_as_float(jl.y);
+    d2_slots<DV>(W, e1min, r, j, alpha, gdmin, false, q, mag);
+    float lb = lam;
+#pragma unroll
+    for (int e = 0; e < DV; ++e)
+      if (r[e] != kNone) lb = lb + (q[e] >= 0 ? -mag[e] : mag[e]);
+    if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
+    float4 mg[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
+    float d[DV], E[DV];
+    col_d1<DV, NM>(r, mg, W.sbits, d);
     e1_all<DV>(lam, d, E);
     float post = lam;
     bool exact = true;
 #pragma unroll
-    for (int e = 0; e < DV; ++e)
-      if (r[e] != kNone) post = post + d2_term<DV>(W, tab, r[e], E[e], alpha, gdmin, false, exact);
-    if (!(post <= 0.f)) return;  // e-hat_j = 0 (eq. (4))
+    for (int e = 0; e < DV; ++e) {
+      if (r[e] == kNone) continue;
+      const bool neg = q[e] >= 0 && ((W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
+      exact = exact && q[e] >= 0;
+      post = post + (neg ? -mag[e] : mag[e]);
+    }
+    if (!(post <= 0.f)) return;
     if (exact) {
       set_column<DV>(W, j, r);
       return;
     }
-    const int q = atomicAdd(&W.nexact, 1);
-    if (q < kMaxExact) W.xpos[q] = pos;
+    const int qx = atomicAdd(&W.nexact, 1);
+    if (qx < kMaxExact) W.xpos[qx] = pos;
 #pragma unroll
     for (int e = 0; e < DV; ++e)
-      if (r[e] != kNone && !bit_of(W.s2bits, r[e]))
-        atomicOr(&W.xbits[r[e] >> 5], 1u << (r[e] & 31));
+      if (r[e] != kNone && q[e] < 0) atomicOr(&W.xbits[r[e] >> 5], 1u << (r[e] & 31));
   });
   wave_sync();
   const int nexact = W.nexact;
@@ -488,97 +585,116 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds& W, const uint4* tab, co
   const int npx = list_pairs(rptr, W.xrows, nx, W, lane);
   if (npx < 0) return false;
   init_row_info(W, W.xrows, nx, W.xbits, W.xpre, kMaxRows, lane);
-  scan_rows<DV>(a, W, tab, W.xrows, npx, W.xbits, W.xpre, kMaxRows, lane);
+  scan_rows<DV>(a, W, W.xrows, npx, W.xbits, W.xpre, kMaxRows, lane);
   if (lane < nexact) {
     const int pos = W.xpos[lane];
     const uint4 rq = a.edge_rows[pos];
     const uint2 jl = a.edge_col[pos];
-    int r[DV];
-    float d[DV], E[DV];
+    float4 mg[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
+    int r[DV], q[DV];
+    float d[DV], E[DV], mag[DV];
     const int j = (int)jl.x;
-    col_d1<DV>(rq, j, tab, W.sbits, r, d);
+    col_rows<DV>(rq, r);
+    d2_slots<DV>(W, e1min, r, j, alpha, gdmin, true, q, mag);
+    col_d1<DV, NM>(r, mg, W.sbits, d);
     const float lam = __uint_as_float(jl.y);
     e1_all<DV>(lam, d, E);
     float post = lam;
-    bool exact = true;
 #pragma unroll
-    for (int e = 0; e < DV; ++e)
-      if (r[e] != kNone) post = post + d2_term<DV>(W, tab, r[e], E[e], alpha, gdmin, true, exact);
+    for (int e = 0; e < DV; ++e) {
+      if (r[e] == kNone) continue;  // (every other slot is in S2 or scanned)
+      const bool neg = (W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31);
+      post = post + (neg ? -mag[e] : mag[e]);
+    }
     if (post <= 0.f) set_column<DV>(W, j, r);
   }
   wave_sync();
   return true;
 }
 
+// e-hat as bytes, V per store: lane c of each pass of 64 stores writes chunk
+// c; one ballot finds the set columns whose chunks fall in the pass.
+// `myj`: the lane's entry of the set, or -1.
 template <int V>
-__device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* row,
-                                                  const WaveLds& W, int nset, int lane) {
+__device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* row, int myj,
+                                                  int lane) {
   const int nchunk = a.n / V;
-  for (int c = lane; c < nchunk; c += 64) {
-    if constexpr (V == 16) {
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
-      for (int q = 0; q < nset; ++q) {
-        const int j = W.set[q];
-        if ((j >> 4) == c) w[(j >> 2) & 3] |= 1u << (8 * (j & 3));
+  const int mych = myj >= 0 ? myj / V : -1;
+  for (int c0 = 0; c0 < nchunk; c0 += 64) {
+    const int c = c0 + lane;
+    unsigned long long mk = __ballot(mych >= c0 && mych < c0 + 64);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    while (mk) {
+      const int q = __builtin_ctzll(mk);
+      mk &= mk - 1ull;
+      const int j = __shfl(myj, q, 64);
+      const uint32_t b = j / V == c ? (V == 1 ? 1u : 1u << (8 * (j & 3))) : 0u;
+      const int wi = V == 16 ? (j >> 2) & 3 : 0;  // word of the chunk
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] |= wi == u ? b : 0u;
+    }
+    if (c < nchunk) {
+      if constexpr (V == 16) {
+        reinterpret_cast<uint4*>(row)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+      } else if constexpr (V == 4) {
+        reinterpret_cast<uint32_t*>(row)[c] = w[0];
+      } else {
+        row[c] = (uint8_t)(w[0] & 1u);
       }
-      reinterpret_cast<uint4*>(row)[c] = make_uint4(w[0], w[1], w[2], w[3]);
-    } else if constexpr (V == 4) {
-      uint32_t w = 0u;
-      for (int q = 0; q < nset; ++q) {
-        const int j = W.set[q];
-        if ((j >> 2) == c) w |= 1u << (8 * (j & 3));
-      }
-      reinterpret_cast<uint32_t*>(row)[c] = w;
-    } else {
-      uint32_t b = 0u;
-      for (int q = 0; q < nset; ++q) b |= W.set[q] == c ? 1u : 0u;
-      row[c] = (uint8_t)b;
     }
   }
 }
 
-// V: bytes per correction store; DV: largest column degree rounded up to
-// an even number.
+// Outputs of a finished shot from W.set: corrections, logical flips
+// (A e-hat), converged flag.
+template <int V>
+__device__ __forceinline__ void write_shot(const ScreenArgs& a, const WaveLds1& W, long long shot,
+                                           int lane) {
+  const int nset = W.nset;
+  const int myj = lane < nset ? W.set[lane] : -1;
+  // (the logical masks are loaded before the stores: a load issued after
+  // them would wait for them too)
+  const unsigned long long lm = myj >= 0 ? a.lmask[myj] : 0ull;
+  write_corrections<V>(a, a.corr + shot * a.n, myj, lane);
+  uint32_t lo = (uint32_t)lm, hi = (uint32_t)(lm >> 32);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo ^= __shfl_xor(lo, o, 64);
+    hi ^= __shfl_xor(hi, o, 64);
+  }
+  const unsigned long long fl = (unsigned long long)lo | ((unsigned long long)hi << 32);
+  if (lane < a.k) a.flips[shot * a.k + lane] = (uint8_t)((fl >> lane) & 1ull);
+  if (lane == 0) a.conv[shot] = 1;
+}
+
+__device__ __forceinline__ void list_dense(const ScreenArgs& a, long long shot) {
+  const int q = __hip_atomic_fetch_add(&a.st->listed, 1, __ATOMIC_RELAXED, AGENT);
+  a.list[q] = (int32_t)shot;
+}
+
+// Iteration 1.  V: bytes per correction store; DV: largest column degree
+// rounded up to an even number.  Wave w takes shots w, w + nwaves, ...;
+// the syndrome of its next shot is loaded during the current one.
 template <int V, int DV>
-__global__ void __launch_bounds__(kScreenBlock, BSD_SCREEN_MIN_WAVES) k_screen(ScreenArgs a) {
+__global__ void __launch_bounds__(kScreenBlock, BSD_S1W) k_screen1(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
-  uint4* tab = reinterpret_cast<uint4*>(sm);
-  int32_t* rptr = reinterpret_cast<int32_t*>(sm + 16 * (size_t)a.m);
-  WaveLds* wl = reinterpret_cast<WaveLds*>(sm + 16 * (size_t)a.m + align16(4 * (size_t)(a.m + 1)));
-  for (int i = threadIdx.x; i < a.m; i += kScreenBlock) tab[i] = a.row_tab[i];
+  int32_t* rptr = reinterpret_cast<int32_t*>(sm);
+  WaveLds1* wl = reinterpret_cast<WaveLds1*>(sm + table_bytes(a.m, 1));
   for (int i = threadIdx.x; i <= a.m; i += kScreenBlock) rptr[i] = a.row_ptr[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  WaveLds& W = wl[wv];
-  // Shots below `nstatic` go to the waves in turn (wave w takes w, w +
-  // nwaves, ...); the rest are claimed one at a time from a counter, so that
-  // waves that drew costly shots (iteration 2) take fewer of the rest.  A
-  // claim is issued one shot ahead and read one shot later, so no wave waits
-  // on it; the syndrome of the next shot is loaded during the current one.
-  const long long nwaves = (long long)gridDim.x * kWaves;
-  const long long nstatic = (a.shots * 3 / 4) / nwaves * nwaves;
-  uint32_t done = 0, done2 = 0, err = 0;
-  auto claim = [&]() -> unsigned long long {  // lane 0's result only
-    return lane == 0 ? __hip_atomic_fetch_add(&a.st->screen_next, 1ull, __ATOMIC_RELAXED, AGENT)
-                     : 0ull;
-  };
-  auto bcast = [&](unsigned long long v) -> long long {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, 0, 64);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), 0, 64);
-    return nstatic + (long long)(((unsigned long long)hi << 32) | lo);
-  };
-  const long long w0 = (long long)blockIdx.x * kWaves + wv;
-  long long shot = w0 < nstatic ? w0 : bcast(claim());
-  long long nxt = shot + nwaves < nstatic ? shot + nwaves : bcast(claim());
+  WaveLds1& W = wl[wv];
+  const long long nwaves = (long long)gridDim.x * kWaves1;
+  uint32_t done = 0, err = 0;
+  long long shot = (long long)blockIdx.x * kWaves1 + wv;
   uint2 sv[kSynRegs];
   if (a.syn8 && shot < a.shots) load_syn_regs(a, shot, lane, sv);
-  for (; shot < a.shots;) {
+  for (; shot < a.shots; shot += nwaves) {
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
     err |= syndrome_bits(a, shot, sv, W, lane);
-    if (a.syn8 && nxt < a.shots) load_syn_regs(a, nxt, lane, sv);
-    // the shot after nxt: static, or a claim read at the end of this one
-    const bool dyn = !(nxt + nwaves < nstatic) && nxt < a.shots;
-    const unsigned long long pend = dyn ? claim() : 0ull;
+    if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
     // Flipped detectors, ascending, and their (row, column) pairs.
     const int nflip = list_rows(W.sbits, a.words_m, W.rows, kMaxRows, W.fpre, lane);
     W.rbits[lane] = W.sbits[lane];
@@ -594,103 +710,145 @@ __global__ void __launch_bounds__(kScreenBlock, BSD_SCREEN_MIN_WAVES) k_screen(S
       // Eq. (3) at t = 1: Lambda_j, then the messages of the rows in
       // ascending order (absent slots add nothing).  The column is kept only
       // by its lowest flipped detector, so that it counts once.
-      for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint2& jl) {
+      constexpr int NM = (DV + 3) / 4;
+      for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
+                                                                  const uint2& jl, const float4 (&mg)[NM]) {
         int r[DV];
         float d[DV];
-        const int j = (int)jl.x;
-        col_d1<DV>(rq, j, tab, W.sbits, r, d);
+        col_rows<DV>(rq, r);
         if (first_in<DV>(W.sbits, r) != i) return;
+        col_d1<DV, NM>(r, mg, W.sbits, d);
         float post = __uint_as_float(jl.y);
 #pragma unroll
         for (int e = 0; e < DV; ++e)
           if (r[e] != kNone) post = post + d[e];
-        if (post <= 0.f) set_column<DV>(W, j, r);  // eq. (4): e-hat_j = 1
+        if (post <= 0.f) set_column<DV>(W, (int)jl.x, r);  // eq. (4): e-hat_j = 1
       });
       wave_sync();
     }
     // Stopping rule: s + H e-hat = 0.
-    bool conv = ok && W.nset <= kScreenMaxSet &&
-                __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
-    bool conv2 = false;
-    if (ok && !conv && a.t2) {
-      conv2 = iteration2<DV>(a, W, tab, rptr, nflip, ncand, lane) && W.nset <= kScreenMaxSet &&
-              __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
-    }
-    if (conv || conv2) {
-      const int nset = W.nset;
-      // (the logical masks are loaded before the stores: a load issued after
-      // them would wait for them too)
-      const unsigned long long lm = lane < nset ? a.lmask[W.set[lane]] : 0ull;
-      write_corrections<V>(a, a.corr + shot * a.n, W, nset, lane);
-      uint32_t lo = (uint32_t)lm, hi = (uint32_t)(lm >> 32);
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        lo ^= __shfl_xor(lo, o, 64);
-        hi ^= __shfl_xor(hi, o, 64);
-      }
-      const unsigned long long fl = (unsigned long long)lo | ((unsigned long long)hi << 32);
-      if (lane < a.k) a.flips[shot * a.k + lane] = (uint8_t)((fl >> lane) & 1ull);
-      if (lane == 0) {
-        a.conv[shot] = 1;
-        if (conv) ++done;
-        else ++done2;
-      }
+    const bool conv = ok && W.nset <= kScreenMaxSet &&
+                      __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
+    if (conv) {
+      write_shot<V>(a, W, shot, lane);
+      ++done;
     } else if (lane == 0) {
-      const int q = __hip_atomic_fetch_add(&a.st->listed, 1, __ATOMIC_RELAXED, AGENT);
-      a.list[q] = (int32_t)shot;
+      if (ok && a.t2) {
+        const int q = __hip_atomic_fetch_add(&a.st->listed2, 1, __ATOMIC_RELAXED, AGENT);
+        a.list2[q] = (int32_t)shot;
+      } else {
+        list_dense(a, shot);
+      }
     }
     if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     wave_sync();  // the next shot reuses this wave's LDS
-    const long long after = dyn ? bcast(pend) : nxt + nwaves;
-    shot = nxt;
-    nxt = after;
   }
-  if (lane == 0 && (done | done2)) {
-    __hip_atomic_fetch_add(&a.st->done, (unsigned long long)(done + done2), __ATOMIC_RELAXED, AGENT);
-    __hip_atomic_fetch_add(&a.st->runs, (unsigned long long)(done + done2), __ATOMIC_RELAXED, AGENT);
-    __hip_atomic_fetch_add(&a.st->iterations, (unsigned long long)(done + 2 * done2),
-                           __ATOMIC_RELAXED, AGENT);
-    if (done2) __hip_atomic_fetch_add(&a.st->done2, done2, __ATOMIC_RELAXED, AGENT);
+  if (lane == 0 && done) {
+    __hip_atomic_fetch_add(&a.st->done, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->runs, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->iterations, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
   }
   if (__ballot(err != 0u) && lane == 0) atomicOr(&a.st->error, 1u);
 }
 
-}  // namespace
-
-size_t screen_lds_bytes(int m) {
-  return 16 * (size_t)m + align16(4 * (size_t)(m + 1)) + kWaves * sizeof(WaveLds);
+// Iteration 2 of the shots k_screen1 listed, claimed one at a time (the
+// claim of the next is issued at the start of the current one).  Their
+// syndromes were checked by k_screen1.
+template <int V, int DV>
+__global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen2(ScreenArgs a) {
+  extern __shared__ __align__(16) char sm[];
+  int32_t* rptr = reinterpret_cast<int32_t*>(sm);
+  float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(a.m + 1)));
+  WaveLds2* wl = reinterpret_cast<WaveLds2*>(sm + table_bytes(a.m, 2));
+  for (int i = threadIdx.x; i <= a.m; i += kScreen2Block) rptr[i] = a.row_ptr[i];
+  for (int i = threadIdx.x; i < a.m; i += kScreen2Block) e1min[i] = a.row_e1min[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  WaveLds2& W = wl[wv];
+  // (written by the previous kernel on this stream)
+  const long long n2 = __hip_atomic_load(&a.st->listed2, __ATOMIC_RELAXED, AGENT);
+  uint32_t done = 0;
+  auto claim = [&]() -> unsigned long long {  // lane 0's result only
+    return lane == 0 ? __hip_atomic_fetch_add(&a.st->screen2_next, 1ull, __ATOMIC_RELAXED, AGENT)
+                     : 0ull;
+  };
+  long long pos = (long long)bcast64(claim());
+  uint2 sv[kSynRegs];
+  while (pos < n2) {
+    const long long shot = a.list2[pos];
+    if (a.syn8) load_syn_regs(a, shot, lane, sv);
+    const unsigned long long pend = claim();
+    const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
+    syndrome_bits(a, shot, sv, W, lane);
+    const int nflip = list_rows(W.sbits, a.words_m, W.rows, kMaxRows, W.fpre, lane);
+    bool ok = nflip <= kMaxRows;
+    int ncand = 0;
+    if (ok) {
+      ncand = list_pairs(rptr, W.rows, nflip, W, lane);
+      ok = ncand >= 0;
+    }
+    ok = ok && iteration2<DV>(a, W, e1min, rptr, nflip, ncand, lane) && W.nset <= kScreenMaxSet &&
+         __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
+    if (ok) {
+      write_shot<V>(a, W, shot, lane);
+      ++done;
+    } else if (lane == 0) {
+      list_dense(a, shot);
+    }
+    if (a.lat && lane == 0) a.lat[shot] += (uint32_t)wall_clock64() - t0;
+    wave_sync();  // the next shot reuses this wave's LDS
+    pos = (long long)bcast64(pend);
+  }
+  if (lane == 0 && done) {
+    __hip_atomic_fetch_add(&a.st->done, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->runs, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->iterations, 2ull * done, __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->done2, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+  }
 }
 
-int screen_blocks_per_cu(int m) {
+size_t lds1(int m) { return table_bytes(m, 1) + kWaves1 * sizeof(WaveLds1); }
+size_t lds2(int m) { return table_bytes(m, 2) + kWaves2 * sizeof(WaveLds2); }
+
+template <int DV>
+hipError_t launch_dv(const ScreenArgs& a, int grid1, int grid2, hipStream_t s) {
+  switch (a.vec) {
+    case 16: hipLaunchKernelGGL((k_screen1<16, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+    case 4: hipLaunchKernelGGL((k_screen1<4, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+    case 1: hipLaunchKernelGGL((k_screen1<1, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.t2) return e;
+  switch (a.vec) {
+    case 16: hipLaunchKernelGGL((k_screen2<16, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+    case 4: hipLaunchKernelGGL((k_screen2<4, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+    case 1: hipLaunchKernelGGL((k_screen2<1, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int screen_blocks_per_cu(int m, int which) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen<16, 8>, kScreenBlock,
-                                                   screen_lds_bytes(m)) != hipSuccess) {
+  const hipError_t e =
+      which == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen1<16, 8>, kScreenBlock, lds1(m))
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen2<16, 8>, kScreen2Block, lds2(m));
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
   return n < 1 ? 1 : n;
 }
 
-namespace {
-template <int DV>
-hipError_t launch_dv(const ScreenArgs& a, int grid, size_t lds, hipStream_t s) {
-  switch (a.vec) {
-    case 16: hipLaunchKernelGGL((k_screen<16, DV>), dim3(grid), dim3(kScreenBlock), lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_screen<4, DV>), dim3(grid), dim3(kScreenBlock), lds, s, a); break;
-    case 1: hipLaunchKernelGGL((k_screen<1, DV>), dim3(grid), dim3(kScreenBlock), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_screen(const ScreenArgs& a, int grid, hipStream_t s) {
-  const size_t lds = screen_lds_bytes(a.m);
+hipError_t launch_screen(const ScreenArgs& a, int grid1, int grid2, hipStream_t s) {
   switch (a.maxdeg_col) {
-    case 1: case 2: return launch_dv<2>(a, grid, lds, s);
-    case 3: case 4: return launch_dv<4>(a, grid, lds, s);
-    case 5: case 6: return launch_dv<6>(a, grid, lds, s);
-    case 7: case 8: return launch_dv<8>(a, grid, lds, s);
+    case 1: case 2: return launch_dv<2>(a, grid1, grid2, s);
+    case 3: case 4: return launch_dv<4>(a, grid1, grid2, s);
+    case 5: case 6: return launch_dv<6>(a, grid1, grid2, s);
+    case 7: case 8: return launch_dv<8>(a, grid1, grid2, s);
     default: return hipErrorInvalidValue;
   }
 }
