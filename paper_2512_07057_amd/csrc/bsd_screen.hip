@@ -38,10 +38,13 @@
 // from.
 //
 // A workgroup keeps the row pointers (and for iteration 2 each row's least
-// zero-syndrome E(1)) in LDS for the whole launch; each wave holds one
-// shot's bit-vectors, row lists and (row, column) pair lists.  Per shot the
-// global reads are its syndrome and, per (row, column) pair, the column, its
-// prior, its rows and the magnitudes of their iteration-1 messages.
+// zero-syndrome E(1)) in LDS for the whole launch.  Each wave holds one
+// shot's syndrome as a byte per row (and for iteration 2 a byte per row
+// naming its entry of the row information), bit-vectors for listing rows,
+// row lists and (row, column) pair lists.  A column's absent row slots read
+// the byte of a row m that is always 0.  Per shot the global reads are its
+// syndrome and, per (row, column) pair, the column, its prior, its rows and
+// the magnitudes of their iteration-1 messages.
 #include <hip/hip_runtime.h>
 
 #include "bsd_internal.h"
@@ -57,9 +60,6 @@ constexpr int kSynRegs = 4;  // 8-byte syndrome loads per lane: m <= 2048
 #ifndef BSD_SCREEN_UNROLL
 #define BSD_SCREEN_UNROLL 4
 #endif
-#ifndef BSD_S1W
-#define BSD_S1W kScreen1MinWaves
-#endif
 #ifndef BSD_SCREEN_UNROLL2
 #define BSD_SCREEN_UNROLL2 2
 #endif
@@ -69,7 +69,6 @@ constexpr int kMaxRows = kScreenMaxFlipped;   // rows of a pair list (flipped ro
 constexpr int kMaxX = 32;                     // S2 rows that did not flip; rows scanned for exact decisions
 constexpr int kMaxExact = 32;                 // columns decided by exact messages at t = 2
 constexpr int kInfo = kMaxRows + kMaxX;       // row info entries: S2 by rank, then scanned rows
-constexpr int kNone = 0xFFFF;                 // absent row slot
 
 // One shot's iteration 1: syndrome and residual bits, the flipped rows and
 // their (row, column) pairs, the set decisions.
@@ -79,7 +78,6 @@ struct WaveLds1 {
   int32_t cst[kMaxRows];               // first CSR position of each listed row
   int32_t coff[kMaxRows];              // index of its first (row, column) pair
   uint16_t rows[kMaxRows];             // listed rows, ascending: flipped rows (then S2)
-  uint16_t fpre[64];                   // flipped rows in earlier words
   uint8_t cmap[kScreenMaxCand];        // listed row of each (row, column) pair
   int32_t set[kScreenMaxSet];          // columns with e-hat_j = 1
   int32_t nset;
@@ -92,8 +90,6 @@ struct WaveLds2 : WaveLds1 {
   uint32_t s2bits[64];                 // rows of S2
   uint32_t xbits[64];                  // S2 rows that did not flip; later rows to scan
   uint16_t xrows[kMaxX];
-  uint16_t s2pre[64];                  // S2 rows in earlier words
-  uint16_t xpre[64];                   // rows of xbits in earlier words
   unsigned long long rk1[kInfo];       // per row: least |E(1)| << 32 | its column,
   uint32_t rm2[kInfo];                 //   second least |E(1)|,
   uint32_t rpar[kInfo];                //   s_i xor the parity of negative E(1)
@@ -103,10 +99,14 @@ struct WaveLds2 : WaveLds1 {
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Per-workgroup tables: the row pointers, and for iteration 2 the least
-// zero-syndrome E(1) of each row.
+// zero-syndrome E(1) of each row (0 for row m).
 __host__ __device__ constexpr size_t table_bytes(int m, int which) {
-  return align16(4 * (size_t)(m + 1)) + (which == 2 ? align16(4 * (size_t)m) : 0);
+  return align16(4 * (size_t)(m + 1)) + (which == 2 ? align16(4 * (size_t)(m + 1)) : 0);
 }
+
+// Per-wave byte maps: the syndrome (rows 0..m), and for iteration 2 the
+// row information entry + 1 of each row (0: none).
+__host__ __device__ constexpr size_t map_bytes(int m) { return align16((size_t)m + 1); }
 
 // Orders this wave's LDS accesses across lanes (the LDS serves a wave's
 // instructions in order; this keeps the compiler from moving them).
@@ -116,26 +116,8 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t bit_of(const uint32_t* bits, int r) {
-  return (bits[r >> 5] >> (r & 31)) & 1u;
-}
-
-// The same for a row slot that may be absent (kNone: 0).  The load is
-// unconditional, so that the loads of a column's slots issue together.
-__device__ __forceinline__ uint32_t bit_at(const uint32_t* bits, int r) {
-  const uint32_t there = r != 0xFFFF ? 1u : 0u;
-  const uint32_t w = bits[(r & 0x7FF) >> 5];  // (kNone reads an unused word)
-  return (w >> (r & 31)) & there;
-}
-
-// Place of row r among the rows set in `bits` (`pre`: set bits in earlier words).
-__device__ __forceinline__ int rank_of(const uint32_t* bits, const uint16_t* pre, int r) {
-  return (int)pre[r >> 5] + __builtin_popcount(bits[r >> 5] & ((1u << (r & 31)) - 1u));
-}
-
-__device__ __forceinline__ int row_at(const uint4& rq, int e) {
-  const uint32_t w = e < 2 ? rq.x : e < 4 ? rq.y : e < 6 ? rq.z : rq.w;
-  return (int)((w >> (16 * (e & 1))) & 0xFFFFu);
+__device__ __forceinline__ void set_bit(uint32_t* bits, int r) {
+  atomicOr(&bits[r >> 5], 1u << (r & 31));
 }
 
 // Exclusive prefix sum over the wave and the total.
@@ -173,11 +155,12 @@ __device__ __forceinline__ void load_syn_regs(const ScreenArgs& a, long long sho
   }
 }
 
-// Syndrome bits into LDS, from registers (8-byte rows) or byte loads;
-// returns nonzero if a byte is neither 0 nor 1.
-__device__ __forceinline__ uint32_t syndrome_bits(const ScreenArgs& a, long long shot,
-                                                  const uint2 (&v)[kSynRegs], WaveLds1& W,
-                                                  int lane) {
+// The syndrome into LDS: bits (W.sbits) and bytes (smap, rows 0..m-1), from
+// registers (8-byte rows) or byte loads; returns nonzero if a byte is
+// neither 0 nor 1.
+__device__ __forceinline__ uint32_t syndrome_in(const ScreenArgs& a, long long shot,
+                                                const uint2 (&v)[kSynRegs], WaveLds1& W,
+                                                uint8_t* smap, int lane) {
   uint32_t bad = 0;
   W.sbits[lane] = 0u;
   wave_sync();
@@ -192,6 +175,7 @@ __device__ __forceinline__ uint32_t syndrome_bits(const ScreenArgs& a, long long
         const uint32_t lo = (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
         const uint32_t hi = (y & 1u) | ((y >> 7) & 2u) | ((y >> 14) & 4u) | ((y >> 21) & 8u);
         sb[d] = (uint8_t)(lo | (hi << 4));
+        reinterpret_cast<uint2*>(smap)[d] = make_uint2(x & 0x01010101u, y & 0x01010101u);
       }
     }
   } else {
@@ -199,23 +183,21 @@ __device__ __forceinline__ uint32_t syndrome_bits(const ScreenArgs& a, long long
     for (int r = lane; r < a.m; r += 64) {
       const uint32_t b = s[r];
       bad |= b & 0xFEu;
-      if (b & 1u) atomicOr(&W.sbits[r >> 5], 1u << (r & 31));
+      smap[r] = (uint8_t)(b & 1u);
+      if (b & 1u) set_bit(W.sbits, r);
     }
   }
   wave_sync();
   return bad;
 }
 
-// The rows set in a row bit-vector, ascending, into `out` (at most `cap`),
-// and each word's count of set rows in earlier words into `pre`; returns
-// how many are set.
+// The rows set in a row bit-vector, ascending, into `out` (at most `cap`);
+// returns how many are set.
 __device__ __forceinline__ int list_rows(const uint32_t* bits, int words, uint16_t* out, int cap,
-                                         uint16_t* pre, int lane) {
+                                         int lane) {
   const uint32_t word = lane < words ? bits[lane] : 0u;
   int total;
-  const int off = wave_excl_scan(__builtin_popcount(word), lane, &total);
-  pre[lane] = (uint16_t)off;
-  int q = off;
+  int q = wave_excl_scan(__builtin_popcount(word), lane, &total);
   for (uint32_t b = word; b; b &= b - 1u, ++q)
     if (q < cap) out[q] = (uint16_t)(lane * 32 + __builtin_ctz(b));
   wave_sync();
@@ -248,7 +230,7 @@ __device__ __forceinline__ int list_pairs(const int32_t* rptr, const uint16_t* r
 // fn(listed row index, row, CSR position, column's rows, (column, Lambda
 // bits), the column's iteration-1 message magnitudes) for every pair of the
 // listed rows, U pairs per lane in flight.  The magnitudes (MAG, 4 per
-// float4, DV of them) are loaded only when asked for.
+// float4) are loaded only when asked for.
 template <int U, int DV, bool MAG, class Fn>
 __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W,
                                           const uint16_t* rows, int np, int lane, Fn fn) {
@@ -287,32 +269,43 @@ __device__ __forceinline__ float mag_at(const float4 (&mg)[NM], int e) {
   return (e & 3) == 0 ? v.x : (e & 3) == 1 ? v.y : (e & 3) == 2 ? v.z : v.w;
 }
 
+// The column's rows in slot order (ascending); absent slots give row m.
 template <int DV>
-__device__ __forceinline__ void col_rows(const uint4& rq, int (&r)[DV]) {
-#pragma unroll
-  for (int e = 0; e < DV; ++e) r[e] = row_at(rq, e);
-}
-
-// Eq. (1) at t = 1 on the edges of a column (rows r[e] ascending, kNone
-// when absent): the magnitude of the row's message (x, or y on the edge of
-// its least |Lambda|), negative when s_i = 1; 0 on absent slots.
-template <int DV, int NM>
-__device__ __forceinline__ void col_d1(const int (&r)[DV], const float4 (&mg)[NM],
-                                       const uint32_t* sbits, float (&d)[DV]) {
+__device__ __forceinline__ void col_rows(const uint4& rq, int m, int (&r)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
-    const float mag = mag_at<NM>(mg, e);
-    d[e] = r[e] != kNone ? (bit_at(sbits, r[e]) ? -mag : mag) : 0.f;
+    const uint32_t w = e < 2 ? rq.x : e < 4 ? rq.y : e < 6 ? rq.z : rq.w;
+    r[e] = min((int)((w >> (16 * (e & 1))) & 0xFFFFu), m);
   }
 }
 
-// The lowest row of the column's rows that is set in `bits`, or kNone.
+// A byte per slot from a row map.
 template <int DV>
-__device__ __forceinline__ int first_in(const uint32_t* bits, const int (&r)[DV]) {
-  int first = kNone;
+__device__ __forceinline__ void col_map(const uint8_t* map, const int (&r)[DV], uint32_t (&b)[DV]) {
 #pragma unroll
-  for (int e = DV - 1; e >= 0; --e) first = bit_at(bits, r[e]) ? r[e] : first;
+  for (int e = 0; e < DV; ++e) b[e] = map[r[e]];
+}
+
+// The lowest row of the slots whose flag is set, or -1.
+template <int DV>
+__device__ __forceinline__ int first_set(const int (&r)[DV], const bool (&f)[DV]) {
+  int first = -1;
+#pragma unroll
+  for (int e = DV - 1; e >= 0; --e) first = f[e] ? r[e] : first;
   return first;
+}
+
+// Eq. (1) at t = 1 on the edges of a column: the magnitude of the row's
+// message (x, or y on the edge of its least |Lambda|; 0 on absent slots),
+// negative when s_i = 1.
+template <int DV, int NM>
+__device__ __forceinline__ void col_d1(const uint32_t (&sb)[DV], const float4 (&mg)[NM],
+                                       float (&d)[DV]) {
+#pragma unroll
+  for (int e = 0; e < DV; ++e) {
+    const float mag = mag_at<NM>(mg, e);
+    d[e] = sb[e] ? -mag : mag;
+  }
 }
 
 // Eq. (2) at t = 1 on edge slot `es` of a column: Lambda_j, then the other
@@ -346,33 +339,26 @@ __device__ __forceinline__ void e1_all(float lam, const float (&d)[DV], float (&
 
 // Adds column j to e-hat: its detectors join s + H e-hat.
 template <int DV>
-__device__ __forceinline__ void set_column(WaveLds1& W, int j, const int (&r)[DV]) {
+__device__ __forceinline__ void set_column(WaveLds1& W, int j, const int (&r)[DV], int m) {
   const int q = atomicAdd(&W.nset, 1);
   if (q < kScreenMaxSet) W.set[q] = j;
 #pragma unroll
   for (int e = 0; e < DV; ++e)
-    if (r[e] != kNone) atomicXor(&W.rbits[r[e] >> 5], 1u << (r[e] & 31));
+    if (r[e] < m) atomicXor(&W.rbits[r[e] >> 5], 1u << (r[e] & 31));
 }
 
-// Per listed row, entry `base` + its rank in (ibits, ipre) of the row info:
-// the message bound (the check phase's starting least values) and s_i.
-__device__ __forceinline__ void init_row_info(WaveLds2& W, const uint16_t* rows, int nrows,
-                                              const uint32_t* ibits, const uint16_t* ipre, int base,
-                                              int lane) {
-  if (lane < nrows) {
-    const int r = rows[lane];
-    const int q = base + rank_of(ibits, ipre, r);
-    W.rk1[q] = ((unsigned long long)__float_as_uint(kLlrMax) << 32) | 0xFFFFFFFFull;
-    W.rm2[q] = __float_as_uint(kLlrMax);
-    W.rpar[q] = bit_of(W.sbits, r);
-  }
-  wave_sync();
+// Row information entry q: the message bound (the check phase's starting
+// least values) and s_i.
+__device__ __forceinline__ void init_info(WaveLds2& W, int q, uint32_t s) {
+  W.rk1[q] = ((unsigned long long)__float_as_uint(kLlrMax) << 32) | 0xFFFFFFFFull;
+  W.rm2[q] = __float_as_uint(kLlrMax);
+  W.rpar[q] = s;
 }
 
-// One E(1) (held by column j) of a row into its info q.  Each edge of the
-// row takes part once: an atomic minimum of (|v|, j) into rk1 returns the
-// previous least, and the larger magnitude of the two goes into rm2, so rm2
-// ends as the least of all magnitudes but one copy of the row minimum.
+// One E(1) (held by column j) of a row into its information q.  Each edge
+// of the row takes part once: an atomic minimum of (|v|, j) into rk1 returns
+// the previous least, and the larger magnitude of the two goes into rm2, so
+// rm2 ends as the least of all magnitudes but one copy of the row minimum.
 // Magnitudes compare as unsigned integers.
 __device__ __forceinline__ void row_info_add(WaveLds2& W, int q, float v, int j) {
   const uint32_t av = __float_as_uint(v) & 0x7FFFFFFFu;
@@ -382,116 +368,107 @@ __device__ __forceinline__ void row_info_add(WaveLds2& W, int q, float v, int j)
   if (__float_as_uint(v) >> 31) atomicXor(&W.rpar[q], 1u);
 }
 
-// Least and second least |E(1)| and the sign parity of the listed rows, E(1)
-// formed exactly on every edge; info at `base` + rank in (ibits, ipre).
+// Row information of the listed rows (entry imap[row] - 1), E(1) formed
+// exactly on every edge of each row.
 template <int DV>
-__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W,
-                                          const uint16_t* rows, int np, const uint32_t* ibits,
-                                          const uint16_t* ipre, int base, int lane) {
+__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap,
+                                          const uint8_t* imap, const uint16_t* rows, int np,
+                                          int lane) {
   constexpr int NM = (DV + 3) / 4;
   for_pairs<kUnroll2, DV, true>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq,
                                                           const uint2& jl, const float4 (&mg)[NM]) {
     int r[DV];
+    uint32_t sb[DV];
     float d[DV];
-    col_rows<DV>(rq, r);
-    col_d1<DV, NM>(r, mg, W.sbits, d);
+    col_rows<DV>(rq, a.m, r);
+    col_map<DV>(smap, r, sb);
+    col_d1<DV, NM>(sb, mg, d);
     int es = 0;
 #pragma unroll
     for (int e = 0; e < DV; ++e) es = r[e] == i ? e : es;
-    row_info_add(W, base + rank_of(ibits, ipre, i), e1_at<DV>(__uint_as_float(jl.y), d, es),
-                 (int)jl.x);
+    row_info_add(W, (int)imap[i] - 1, e1_at<DV>(__uint_as_float(jl.y), d, es), (int)jl.x);
   });
   wave_sync();
 }
 
-// Magnitude of eq. (1) at t = 2 that a scanned row (info q) sends to column
-// j: alpha * second least |E(1)| to the column holding the least, alpha *
-// least to the others, clamped.  (When another column ties for the least,
-// both are equal.)
+// Magnitude of eq. (1) at t = 2 that a row with information q sends to
+// column j: alpha * second least |E(1)| to the column holding the least,
+// alpha * least to the others, clamped.  (When another column ties for the
+// least, both are equal.)
 __device__ __forceinline__ float d2_mag(const WaveLds2& W, int q, int j, float alpha) {
   const unsigned long long k1 = W.rk1[q];
-  const float m = (int)(uint32_t)k1 == j ? __uint_as_float(W.rm2[q])
-                                         : __uint_as_float((uint32_t)(k1 >> 32));
-  return fminf(alpha * m, kLlrMax);
+  const float mm = (int)(uint32_t)k1 == j ? __uint_as_float(W.rm2[q])
+                                          : __uint_as_float((uint32_t)(k1 >> 32));
+  return fminf(alpha * mm, kLlrMax);
 }
 
-// Info index of row r (not kNone) for eq. (1) at t = 2, or -1 when the row
-// is neither in S2 nor (with `scanned`) among the scanned rows.  The loads
-// do not depend on the tests.
-__device__ __forceinline__ int info_of(const WaveLds2& W, int r, bool scanned) {
-  const uint32_t bit = 1u << (r & 31), below = bit - 1u;
-  const uint32_t w = W.s2bits[r >> 5];
-  const int q = (int)W.s2pre[r >> 5] + __builtin_popcount(w & below);
-  if (!scanned) return (w & bit) ? q : -1;
-  const uint32_t xw = W.xbits[r >> 5];
-  const int qx = kMaxRows + (int)W.xpre[r >> 5] + __builtin_popcount(xw & below);
-  return (w & bit) ? q : (xw & bit) ? qx : -1;
-}
-
-// Lower bound of the message a row outside S2 sends at t = 2.
-__device__ __forceinline__ float d2_lb(const float* e1min, int r, float alpha, float gdmin) {
-  return fminf(alpha * fminf(e1min[r], gdmin), kLlrMax);
-}
-
-// Per slot of a column next to S2: the row's info index (-1 outside S2 and
-// for absent slots), the magnitude of its t = 2 message to column j (S2
-// rows) or the lower bound of it (other rows).
+// Per slot of a column next to S2: the row's information entry (-1 outside
+// S2 and, with `scanned`, the scanned rows), and the magnitude of its t = 2
+// message to column j (those rows) or a lower bound of it (other rows: 0 on
+// absent slots).
 template <int DV>
-__device__ __forceinline__ void d2_slots(const WaveLds2& W, const float* e1min, const int (&r)[DV],
-                                         int j, float alpha, float gdmin, bool scanned,
-                                         int (&q)[DV], float (&mag)[DV]) {
+__device__ __forceinline__ void d2_slots(const WaveLds2& W, const uint8_t* imap, const float* e1min,
+                                         const int (&r)[DV], int j, float alpha, float gdmin,
+                                         bool scanned, int (&q)[DV], float (&mag)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
-    const bool there = r[e] != kNone;
-    const int rs = there ? r[e] : 0;
-    const int qe = info_of(W, rs, scanned);
-    q[e] = there ? qe : -1;
-    const float lb = d2_lb(e1min, rs, alpha, gdmin);
-    const float m = d2_mag(W, qe >= 0 ? qe : 0, j, alpha);
-    mag[e] = qe >= 0 ? m : lb;
+    const int v = (int)imap[r[e]] - 1;
+    q[e] = (v >= 0 && (scanned || v < kMaxRows)) ? v : -1;
+    const float lb = fminf(alpha * fminf(e1min[r[e]], gdmin), kLlrMax);
+    const float mm = d2_mag(W, q[e] >= 0 ? q[e] : 0, j, alpha);
+    mag[e] = q[e] >= 0 ? mm : lb;
   }
 }
 
 // Iteration 2 of a shot whose iteration 1 did not converge (W.rows holds its
-// `nflip` flipped rows and W.cmap / cst / coff their `ncand` pairs).  Leaves
-// e-hat(2) in W.set and s + H e-hat(2) in W.rbits; returns false when a list
-// overflowed (the shot then goes to the dense decoder).
+// `nflip` flipped rows and W.cmap / cst / coff their `ncand` pairs; imap is
+// all 0).  Leaves e-hat(2) in W.set and s + H e-hat(2) in W.rbits; returns
+// false when a list overflowed (the shot then goes to the dense decoder).
 template <int DV>
-__device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min, const int32_t* rptr,
-                           int nflip, int ncand, int lane) {
-  const int words = a.words_m;
+__device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap, uint8_t* imap,
+                           const float* e1min, const int32_t* rptr, int nflip, int ncand, int lane) {
+  constexpr int NM = (DV + 3) / 4;
+  const int words = a.words_m, m = a.m;
   const float alpha = a.alpha2;
   // E(1) on every edge of the columns of flipped detectors.  Rows receiving
   // a negative one join S2 (with the flipped rows); the least non-negative
   // one bounds the E(1) that rows outside S2 receive from these columns.
-  // These are all the edges of the flipped rows, whose row info is formed
-  // here (at their rank among the flipped rows).
+  // These are all the edges of the flipped rows, whose row information is
+  // formed here (entry: rank among the flipped rows).
   W.s2bits[lane] = W.sbits[lane];
-  init_row_info(W, W.rows, nflip, W.sbits, W.fpre, 0, lane);
+  if (lane < nflip) {
+    imap[W.rows[lane]] = (uint8_t)(lane + 1);
+    init_info(W, lane, 1u);
+  }
+  wave_sync();
   float gmin = kLlrMax;
-  constexpr int NM = (DV + 3) / 4;
   for_pairs<kUnroll2, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
                                                                const uint2& jl, const float4 (&mg)[NM]) {
     int r[DV];
+    uint32_t sb[DV];
+    bool fl[DV];
     float d[DV], E[DV];
     const int j = (int)jl.x;
-    col_rows<DV>(rq, r);
-    if (first_in<DV>(W.sbits, r) != i) return;  // the column's lowest flipped row takes it
-    col_d1<DV, NM>(r, mg, W.sbits, d);
+    col_rows<DV>(rq, m, r);
+    col_map<DV>(smap, r, sb);
+#pragma unroll
+    for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
+    if (first_set<DV>(r, fl) != i) return;  // the column's lowest flipped row takes it
+    col_d1<DV, NM>(sb, mg, d);
     e1_all<DV>(__uint_as_float(jl.y), d, E);
 #pragma unroll
     for (int e = 0; e < DV; ++e) {
-      if (r[e] == kNone) continue;
+      if (r[e] >= m) continue;
       if (__float_as_uint(E[e]) >> 31)
-        atomicOr(&W.s2bits[r[e] >> 5], 1u << (r[e] & 31));
+        set_bit(W.s2bits, r[e]);
       else
         gmin = fminf(gmin, E[e]);
-      if (bit_of(W.sbits, r[e])) row_info_add(W, rank_of(W.sbits, W.fpre, r[e]), E[e], j);
+      if (sb[e]) row_info_add(W, (int)imap[r[e]] - 1, E[e], j);
     }
   });
   wave_sync();
   const float gdmin = wave_min(gmin);
-  // S2, ascending; the flipped rows' info moves to their rank in S2.
+  // S2, ascending; the flipped rows' information moves to their rank in S2.
   int frow = 0;
   unsigned long long fk1 = 0ull;
   uint32_t fm2 = 0u, fpar = 0u;
@@ -502,23 +479,25 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min,
     fpar = W.rpar[lane];
   }
   wave_sync();
-  const int ns2 = list_rows(W.s2bits, words, W.rows, kMaxRows, W.s2pre, lane);
+  const int ns2 = list_rows(W.s2bits, words, W.rows, kMaxRows, lane);
   if (ns2 > kMaxRows) return false;
+  if (lane < ns2) imap[W.rows[lane]] = (uint8_t)(lane + 1);
+  wave_sync();
   if (lane < nflip) {
-    const int q = rank_of(W.s2bits, W.s2pre, frow);
+    const int q = (int)imap[frow] - 1;
     W.rk1[q] = fk1;
     W.rm2[q] = fm2;
     W.rpar[q] = fpar;
   }
-  // The S2 rows that did not flip get their info from scans of their edges.
+  // The S2 rows that did not flip get theirs from scans of their edges.
   W.xbits[lane] = W.s2bits[lane] & ~W.sbits[lane];
   wave_sync();
-  const int nn = list_rows(W.xbits, words, W.xrows, kMaxX, W.xpre, lane);
+  const int nn = list_rows(W.xbits, words, W.xrows, kMaxX, lane);
   if (nn > kMaxX) return false;
-  init_row_info(W, W.xrows, nn, W.s2bits, W.s2pre, 0, lane);
+  if (lane < nn) init_info(W, (int)imap[W.xrows[lane]] - 1, 0u);
   const int npn = list_pairs(rptr, W.xrows, nn, W, lane);
   if (npn < 0) return false;
-  scan_rows<DV>(a, W, W.xrows, npn, W.s2bits, W.s2pre, 0, lane);
+  scan_rows<DV>(a, W, smap, imap, W.xrows, npn, lane);
   const int np = list_pairs(rptr, W.rows, ns2, W, lane);
   if (np < 0) return false;
 
@@ -537,42 +516,45 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min,
   for_pairs<kUnroll2, DV, false>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq,
                                                               const uint2& jl, const float4 (&)[1]) {
     int r[DV], q[DV];
+    bool in2[DV];
     float mag[DV];
     const int j = (int)jl.x;
-    col_rows<DV>(rq, r);
-    if (first_in<DV>(W.s2bits, r) != i) return;
+    col_rows<DV>(rq, m, r);
+    d2_slots<DV>(W, imap, e1min, r, j, alpha, gdmin, false, q, mag);
+#pragma unroll
+    for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
+    if (first_set<DV>(r, in2) != i) return;
     const float lam = __uint_as_float(jl.y);
-    d2_slots<DV>(W, e1min, r, j, alpha, gdmin, false, q, mag);
     float lb = lam;
 #pragma unroll
-    for (int e = 0; e < DV; ++e)
-      if (r[e] != kNone) lb = lb + (q[e] >= 0 ? -mag[e] : mag[e]);
+    for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
     if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
     float4 mg[NM];
 #pragma unroll
     for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
+    uint32_t sb[DV];
     float d[DV], E[DV];
-    col_d1<DV, NM>(r, mg, W.sbits, d);
+    col_map<DV>(smap, r, sb);
+    col_d1<DV, NM>(sb, mg, d);
     e1_all<DV>(lam, d, E);
     float post = lam;
     bool exact = true;
 #pragma unroll
     for (int e = 0; e < DV; ++e) {
-      if (r[e] == kNone) continue;
-      const bool neg = q[e] >= 0 && ((W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
-      exact = exact && q[e] >= 0;
+      const bool neg = in2[e] && ((W.rpar[in2[e] ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
+      exact = exact && (in2[e] || r[e] >= m);
       post = post + (neg ? -mag[e] : mag[e]);
     }
     if (!(post <= 0.f)) return;
     if (exact) {
-      set_column<DV>(W, j, r);
+      set_column<DV>(W, j, r, m);
       return;
     }
     const int qx = atomicAdd(&W.nexact, 1);
     if (qx < kMaxExact) W.xpos[qx] = pos;
 #pragma unroll
     for (int e = 0; e < DV; ++e)
-      if (r[e] != kNone && q[e] < 0) atomicOr(&W.xbits[r[e] >> 5], 1u << (r[e] & 31));
+      if (r[e] < m && !in2[e]) set_bit(W.xbits, r[e]);
   });
   wave_sync();
   const int nexact = W.nexact;
@@ -580,12 +562,15 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min,
   if (nexact > kMaxExact) return false;
 
   // Exact messages for the listed columns: scan their rows outside S2.
-  const int nx = list_rows(W.xbits, words, W.xrows, kMaxX, W.xpre, lane);
+  const int nx = list_rows(W.xbits, words, W.xrows, kMaxX, lane);
   if (nx > kMaxX) return false;
+  if (lane < nx) {
+    imap[W.xrows[lane]] = (uint8_t)(kMaxRows + lane + 1);
+    init_info(W, kMaxRows + lane, 0u);
+  }
   const int npx = list_pairs(rptr, W.xrows, nx, W, lane);
   if (npx < 0) return false;
-  init_row_info(W, W.xrows, nx, W.xbits, W.xpre, kMaxRows, lane);
-  scan_rows<DV>(a, W, W.xrows, npx, W.xbits, W.xpre, kMaxRows, lane);
+  scan_rows<DV>(a, W, smap, imap, W.xrows, npx, lane);
   if (lane < nexact) {
     const int pos = W.xpos[lane];
     const uint4 rq = a.edge_rows[pos];
@@ -594,21 +579,22 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float* e1min,
 #pragma unroll
     for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
     int r[DV], q[DV];
+    uint32_t sb[DV];
     float d[DV], E[DV], mag[DV];
     const int j = (int)jl.x;
-    col_rows<DV>(rq, r);
-    d2_slots<DV>(W, e1min, r, j, alpha, gdmin, true, q, mag);
-    col_d1<DV, NM>(r, mg, W.sbits, d);
+    col_rows<DV>(rq, m, r);
+    d2_slots<DV>(W, imap, e1min, r, j, alpha, gdmin, true, q, mag);
+    col_map<DV>(smap, r, sb);
+    col_d1<DV, NM>(sb, mg, d);
     const float lam = __uint_as_float(jl.y);
     e1_all<DV>(lam, d, E);
     float post = lam;
 #pragma unroll
-    for (int e = 0; e < DV; ++e) {
-      if (r[e] == kNone) continue;  // (every other slot is in S2 or scanned)
-      const bool neg = (W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31);
+    for (int e = 0; e < DV; ++e) {  // (every present slot is in S2 or scanned)
+      const bool neg = q[e] >= 0 && ((W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
       post = post + (neg ? -mag[e] : mag[e]);
     }
-    if (post <= 0.f) set_column<DV>(W, j, r);
+    if (post <= 0.f) set_column<DV>(W, j, r, m);
   }
   wave_sync();
   return true;
@@ -674,18 +660,33 @@ __device__ __forceinline__ void list_dense(const ScreenArgs& a, long long shot) 
   a.list[q] = (int32_t)shot;
 }
 
+// Flipped rows and their pairs; false when the lists overflow.
+__device__ __forceinline__ bool flipped_pairs(const ScreenArgs& a, WaveLds1& W, const int32_t* rptr,
+                                              int lane, int* nflip, int* ncand) {
+  *nflip = list_rows(W.sbits, a.words_m, W.rows, kMaxRows, lane);
+  *ncand = 0;
+  if (*nflip > kMaxRows) return false;
+  *ncand = list_pairs(rptr, W.rows, *nflip, W, lane);
+  return *ncand >= 0;
+}
+
 // Iteration 1.  V: bytes per correction store; DV: largest column degree
 // rounded up to an even number.  Wave w takes shots w, w + nwaves, ...;
 // the syndrome of its next shot is loaded during the current one.
 template <int V, int DV>
-__global__ void __launch_bounds__(kScreenBlock, BSD_S1W) k_screen1(ScreenArgs a) {
+__global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
+  constexpr int NM = (DV + 3) / 4;
+  const int m = a.m;
   int32_t* rptr = reinterpret_cast<int32_t*>(sm);
-  WaveLds1* wl = reinterpret_cast<WaveLds1*>(sm + table_bytes(a.m, 1));
-  for (int i = threadIdx.x; i <= a.m; i += kScreenBlock) rptr[i] = a.row_ptr[i];
-  __syncthreads();
+  WaveLds1* wl = reinterpret_cast<WaveLds1*>(sm + table_bytes(m, 1));
+  for (int i = threadIdx.x; i <= m; i += kScreenBlock) rptr[i] = a.row_ptr[i];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   WaveLds1& W = wl[wv];
+  uint8_t* smap = reinterpret_cast<uint8_t*>(sm + table_bytes(m, 1) + align16(kWaves1 * sizeof(WaveLds1))) +
+                  wv * map_bytes(m);
+  if (lane == 0) smap[m] = 0;  // absent row slots
+  __syncthreads();
   const long long nwaves = (long long)gridDim.x * kWaves1;
   uint32_t done = 0, err = 0;
   long long shot = (long long)blockIdx.x * kWaves1 + wv;
@@ -693,36 +694,32 @@ __global__ void __launch_bounds__(kScreenBlock, BSD_S1W) k_screen1(ScreenArgs a)
   if (a.syn8 && shot < a.shots) load_syn_regs(a, shot, lane, sv);
   for (; shot < a.shots; shot += nwaves) {
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
-    err |= syndrome_bits(a, shot, sv, W, lane);
+    err |= syndrome_in(a, shot, sv, W, smap, lane);
     if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
-    // Flipped detectors, ascending, and their (row, column) pairs.
-    const int nflip = list_rows(W.sbits, a.words_m, W.rows, kMaxRows, W.fpre, lane);
     W.rbits[lane] = W.sbits[lane];
     if (lane == 0) W.nset = 0;
-    wave_sync();
-    bool ok = nflip <= kMaxRows;
-    int ncand = 0;
-    if (ok) {
-      ncand = list_pairs(rptr, W.rows, nflip, W, lane);
-      ok = ncand >= 0;
-    }
+    int nflip, ncand;
+    const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
     if (ok) {
       // Eq. (3) at t = 1: Lambda_j, then the messages of the rows in
-      // ascending order (absent slots add nothing).  The column is kept only
-      // by its lowest flipped detector, so that it counts once.
-      constexpr int NM = (DV + 3) / 4;
+      // ascending order (absent slots add 0).  The column is kept only by
+      // its lowest flipped detector, so that it counts once.
       for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
                                                                   const uint2& jl, const float4 (&mg)[NM]) {
         int r[DV];
+        uint32_t sb[DV];
+        bool fl[DV];
         float d[DV];
-        col_rows<DV>(rq, r);
-        if (first_in<DV>(W.sbits, r) != i) return;
-        col_d1<DV, NM>(r, mg, W.sbits, d);
+        col_rows<DV>(rq, m, r);
+        col_map<DV>(smap, r, sb);
+#pragma unroll
+        for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
+        col_d1<DV, NM>(sb, mg, d);
         float post = __uint_as_float(jl.y);
 #pragma unroll
-        for (int e = 0; e < DV; ++e)
-          if (r[e] != kNone) post = post + d[e];
-        if (post <= 0.f) set_column<DV>(W, (int)jl.x, r);  // eq. (4): e-hat_j = 1
+        for (int e = 0; e < DV; ++e) post = post + d[e];
+        if (first_set<DV>(r, fl) == i && post <= 0.f)  // eq. (4): e-hat_j = 1
+          set_column<DV>(W, (int)jl.x, r, m);
       });
       wave_sync();
     }
@@ -757,14 +754,21 @@ __global__ void __launch_bounds__(kScreenBlock, BSD_S1W) k_screen1(ScreenArgs a)
 template <int V, int DV>
 __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen2(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
+  const int m = a.m;
   int32_t* rptr = reinterpret_cast<int32_t*>(sm);
-  float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(a.m + 1)));
-  WaveLds2* wl = reinterpret_cast<WaveLds2*>(sm + table_bytes(a.m, 2));
-  for (int i = threadIdx.x; i <= a.m; i += kScreen2Block) rptr[i] = a.row_ptr[i];
-  for (int i = threadIdx.x; i < a.m; i += kScreen2Block) e1min[i] = a.row_e1min[i];
-  __syncthreads();
+  float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(m + 1)));
+  WaveLds2* wl = reinterpret_cast<WaveLds2*>(sm + table_bytes(m, 2));
+  for (int i = threadIdx.x; i <= m; i += kScreen2Block) {
+    rptr[i] = a.row_ptr[i];
+    e1min[i] = i < m ? a.row_e1min[i] : 0.f;  // (row m: absent slots, bound 0)
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   WaveLds2& W = wl[wv];
+  uint8_t* smap = reinterpret_cast<uint8_t*>(sm + table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2))) +
+                  wv * 2 * map_bytes(m);
+  uint8_t* imap = smap + map_bytes(m);
+  if (lane == 0) smap[m] = 0;
+  __syncthreads();
   // (written by the previous kernel on this stream)
   const long long n2 = __hip_atomic_load(&a.st->listed2, __ATOMIC_RELAXED, AGENT);
   uint32_t done = 0;
@@ -779,16 +783,13 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen2(Scr
     if (a.syn8) load_syn_regs(a, shot, lane, sv);
     const unsigned long long pend = claim();
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
-    syndrome_bits(a, shot, sv, W, lane);
-    const int nflip = list_rows(W.sbits, a.words_m, W.rows, kMaxRows, W.fpre, lane);
-    bool ok = nflip <= kMaxRows;
-    int ncand = 0;
-    if (ok) {
-      ncand = list_pairs(rptr, W.rows, nflip, W, lane);
-      ok = ncand >= 0;
-    }
-    ok = ok && iteration2<DV>(a, W, e1min, rptr, nflip, ncand, lane) && W.nset <= kScreenMaxSet &&
-         __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
+    for (int q = lane; q < (int)map_bytes(m) / 16; q += 64)
+      reinterpret_cast<uint4*>(imap)[q] = make_uint4(0u, 0u, 0u, 0u);
+    syndrome_in(a, shot, sv, W, smap, lane);
+    int nflip, ncand;
+    bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
+    ok = ok && iteration2<DV>(a, W, smap, imap, e1min, rptr, nflip, ncand, lane) &&
+         W.nset <= kScreenMaxSet && __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
     if (ok) {
       write_shot<V>(a, W, shot, lane);
       ++done;
@@ -807,8 +808,10 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen2(Scr
   }
 }
 
-size_t lds1(int m) { return table_bytes(m, 1) + kWaves1 * sizeof(WaveLds1); }
-size_t lds2(int m) { return table_bytes(m, 2) + kWaves2 * sizeof(WaveLds2); }
+size_t lds1(int m) { return table_bytes(m, 1) + align16(kWaves1 * sizeof(WaveLds1)) + kWaves1 * map_bytes(m); }
+size_t lds2(int m) {
+  return table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2)) + kWaves2 * 2 * map_bytes(m);
+}
 
 template <int DV>
 hipError_t launch_dv(const ScreenArgs& a, int grid1, int grid2, hipStream_t s) {
