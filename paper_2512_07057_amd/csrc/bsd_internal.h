@@ -219,7 +219,8 @@ struct ScreenArgs {
   uint32_t* lat;               // or NULL
   BatchState* st;              // error, done, runs, iterations, listed, listed2
   int32_t* list;               // [shots] shots for the dense decoder
-  int32_t* list2;              // [shots] shots for the iteration-2 screen
+  int32_t* list2;              // [shots] shots for iteration 2 of the screen (shot + 1; 0 until
+                               //   written; zeroed by the reset kernel)
 };
 constexpr int kScreenBlock = 512;        // iteration 1: eight shots in flight per workgroup
 constexpr int kScreen1MinWaves = 4;      // iteration 1: waves per SIMD the registers must allow

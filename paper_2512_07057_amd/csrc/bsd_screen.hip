@@ -1,8 +1,7 @@
 // Sparse screen of the first two iterations of the initial BP run
 // (Appendix A, eqs. (1)-(4) and the stopping rule at t = 1 and t = 2), one
-// wavefront per shot, in two kernels: k_screen1 for iteration 1 of every
-// shot, k_screen2 for iteration 2 of the shots that iteration 1 leaves
-// unconverged.
+// wavefront per shot: k_screen12 for both iterations (k_screen1 when only
+// iteration 1 is screened).
 //
 // Iteration 1.  From E(0) = Lambda with every Lambda_j > 0 every sign in
 // eq. (1) except (-1)^{s_i} is +1, so at t = 1 detector i sends
@@ -95,6 +94,17 @@ struct WaveLds2 : WaveLds1 {
   uint32_t rpar[kInfo];                //   s_i xor the parity of negative E(1)
   int32_t xpos[kMaxExact];             // a CSR position of each column decided exactly
 };
+
+// A workgroup's shots for iteration 2 (shot + 1; 0 until written).
+constexpr int kWgList = 448;
+struct WgList {
+  int32_t shot[kWgList];
+  int32_t count;     // positions reserved by listers
+  int32_t taken;     // positions taken by waves
+  int32_t finished;  // waves done with iteration 1
+  int32_t pad;
+};
+static_assert(sizeof(WgList) % 16 == 0, "keeps the byte maps 16-byte aligned");
 
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -670,9 +680,9 @@ __device__ __forceinline__ bool flipped_pairs(const ScreenArgs& a, WaveLds1& W, 
   return *ncand >= 0;
 }
 
-// Iteration 1.  V: bytes per correction store; DV: largest column degree
-// rounded up to an even number.  Wave w takes shots w, w + nwaves, ...;
-// the syndrome of its next shot is loaded during the current one.
+// Iteration 1 only.  V: bytes per correction store; DV: largest column
+// degree rounded up to an even number.  Wave w takes shots w, w + nwaves,
+// ...; the syndrome of its next shot is loaded during the current one.
 template <int V, int DV>
 __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
@@ -730,12 +740,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
       write_shot<V>(a, W, shot, lane);
       ++done;
     } else if (lane == 0) {
-      if (ok && a.t2) {
-        const int q = __hip_atomic_fetch_add(&a.st->listed2, 1, __ATOMIC_RELAXED, AGENT);
-        a.list2[q] = (int32_t)shot;
-      } else {
-        list_dense(a, shot);
-      }
+      list_dense(a, shot);
     }
     if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     wave_sync();  // the next shot reuses this wave's LDS
@@ -748,86 +753,154 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
   if (__ballot(err != 0u) && lane == 0) atomicOr(&a.st->error, 1u);
 }
 
-// Iteration 2 of the shots k_screen1 listed, claimed one at a time (the
-// claim of the next is issued at the start of the current one).  Their
-// syndromes were checked by k_screen1.
+// Iterations 1 and 2 in one kernel.  Each wave first takes its share of
+// the shots for iteration 1 (wave w: shots w, w + nwaves, ...) and lists in
+// its workgroup's LDS those that need iteration 2; then the workgroup's
+// waves take listed shots one at a time, so that waves that finish early
+// take the costly iteration-2 shots of their siblings.  A wave may wait
+// only for waves of its own workgroup (all resident together): a taken
+// position is served once a sibling lists a shot there, or given up when
+// every sibling has finished iteration 1 and the list is shorter.
 template <int V, int DV>
-__global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen2(ScreenArgs a) {
+__global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
+  constexpr int NM = (DV + 3) / 4;
   const int m = a.m;
   int32_t* rptr = reinterpret_cast<int32_t*>(sm);
   float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(m + 1)));
   WaveLds2* wl = reinterpret_cast<WaveLds2*>(sm + table_bytes(m, 2));
+  WgList* gl = reinterpret_cast<WgList*>(sm + table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2)));
   for (int i = threadIdx.x; i <= m; i += kScreen2Block) {
     rptr[i] = a.row_ptr[i];
     e1min[i] = i < m ? a.row_e1min[i] : 0.f;  // (row m: absent slots, bound 0)
   }
+  for (int i = threadIdx.x; i < kWgList; i += kScreen2Block) gl->shot[i] = 0;
+  if (threadIdx.x == 0) gl->count = gl->taken = gl->finished = 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   WaveLds2& W = wl[wv];
-  uint8_t* smap = reinterpret_cast<uint8_t*>(sm + table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2))) +
-                  wv * 2 * map_bytes(m);
+  uint8_t* smap = reinterpret_cast<uint8_t*>(gl + 1) + wv * 2 * map_bytes(m);
   uint8_t* imap = smap + map_bytes(m);
-  if (lane == 0) smap[m] = 0;
+  if (lane == 0) smap[m] = 0;  // absent row slots
   __syncthreads();
-  // (written by the previous kernel on this stream)
-  const long long n2 = __hip_atomic_load(&a.st->listed2, __ATOMIC_RELAXED, AGENT);
-  uint32_t done = 0;
-  auto claim = [&]() -> unsigned long long {  // lane 0's result only
-    return lane == 0 ? __hip_atomic_fetch_add(&a.st->screen2_next, 1ull, __ATOMIC_RELAXED, AGENT)
-                     : 0ull;
-  };
-  long long pos = (long long)bcast64(claim());
+  const long long nwaves = (long long)gridDim.x * kWaves2;
+  uint32_t done = 0, done2 = 0, err = 0;
+  long long shot = (long long)blockIdx.x * kWaves2 + wv;
   uint2 sv[kSynRegs];
-  while (pos < n2) {
-    const long long shot = a.list2[pos];
-    if (a.syn8) load_syn_regs(a, shot, lane, sv);
-    const unsigned long long pend = claim();
+  if (a.syn8 && shot < a.shots) load_syn_regs(a, shot, lane, sv);
+  for (; shot < a.shots; shot += nwaves) {
+    const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
+    err |= syndrome_in(a, shot, sv, W, smap, lane);
+    if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
+    W.rbits[lane] = W.sbits[lane];
+    if (lane == 0) W.nset = 0;
+    int nflip, ncand;
+    const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
+    if (ok) {
+      for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
+                                                                  const uint2& jl, const float4 (&mg)[NM]) {
+        int r[DV];
+        uint32_t sb[DV];
+        bool fl[DV];
+        float d[DV];
+        col_rows<DV>(rq, m, r);
+        col_map<DV>(smap, r, sb);
+#pragma unroll
+        for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
+        col_d1<DV, NM>(sb, mg, d);
+        float post = __uint_as_float(jl.y);
+#pragma unroll
+        for (int e = 0; e < DV; ++e) post = post + d[e];
+        if (first_set<DV>(r, fl) == i && post <= 0.f) set_column<DV>(W, (int)jl.x, r, m);
+      });
+      wave_sync();
+    }
+    const bool conv = ok && W.nset <= kScreenMaxSet &&
+                      __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
+    if (conv) {
+      write_shot<V>(a, W, shot, lane);
+      ++done;
+    } else if (lane == 0) {
+      const int q = ok ? atomicAdd(&gl->count, 1) : kWgList;
+      if (q < kWgList)
+        __hip_atomic_store(&gl->shot[q], (int32_t)shot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        list_dense(a, shot);
+    }
+    if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
+    wave_sync();  // the next shot reuses this wave's LDS
+  }
+  if (lane == 0) atomicAdd(&gl->finished, 1);
+  // Iteration 2 of the workgroup's listed shots.
+  for (;;) {
+    int s2 = -1;
+    if (lane == 0) {
+      const int c = atomicAdd(&gl->taken, 1);
+      for (;;) {
+        const int v = __hip_atomic_load(&gl->shot[c < kWgList ? c : 0], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c < kWgList && v != 0) {
+          s2 = v - 1;
+          break;
+        }
+        // (count is final once every wave has finished iteration 1)
+        const int fin = __hip_atomic_load(&gl->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int cnt = __hip_atomic_load(&gl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (c >= kWgList || (fin == kWaves2 && c >= cnt)) break;
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    s2 = __shfl(s2, 0, 64);
+    if (s2 < 0) break;
+    if (a.syn8) load_syn_regs(a, s2, lane, sv);
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
     for (int q = lane; q < (int)map_bytes(m) / 16; q += 64)
       reinterpret_cast<uint4*>(imap)[q] = make_uint4(0u, 0u, 0u, 0u);
-    syndrome_in(a, shot, sv, W, smap, lane);
+    syndrome_in(a, s2, sv, W, smap, lane);
     int nflip, ncand;
     bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
     ok = ok && iteration2<DV>(a, W, smap, imap, e1min, rptr, nflip, ncand, lane) &&
          W.nset <= kScreenMaxSet && __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
     if (ok) {
-      write_shot<V>(a, W, shot, lane);
-      ++done;
+      write_shot<V>(a, W, s2, lane);
+      ++done2;
     } else if (lane == 0) {
-      list_dense(a, shot);
+      list_dense(a, s2);
     }
-    if (a.lat && lane == 0) a.lat[shot] += (uint32_t)wall_clock64() - t0;
-    wave_sync();  // the next shot reuses this wave's LDS
-    pos = (long long)bcast64(pend);
+    if (a.lat && lane == 0) a.lat[s2] += (uint32_t)wall_clock64() - t0;
+    wave_sync();
   }
-  if (lane == 0 && done) {
-    __hip_atomic_fetch_add(&a.st->done, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
-    __hip_atomic_fetch_add(&a.st->runs, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
-    __hip_atomic_fetch_add(&a.st->iterations, 2ull * done, __ATOMIC_RELAXED, AGENT);
-    __hip_atomic_fetch_add(&a.st->done2, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
+  if (lane == 0 && (done | done2)) {
+    __hip_atomic_fetch_add(&a.st->done, (unsigned long long)(done + done2), __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->runs, (unsigned long long)(done + done2), __ATOMIC_RELAXED, AGENT);
+    __hip_atomic_fetch_add(&a.st->iterations, (unsigned long long)(done + 2 * done2),
+                           __ATOMIC_RELAXED, AGENT);
+    if (done2) __hip_atomic_fetch_add(&a.st->done2, (unsigned long long)done2, __ATOMIC_RELAXED, AGENT);
   }
+  if (__ballot(err != 0u) && lane == 0) atomicOr(&a.st->error, 1u);
 }
 
 size_t lds1(int m) { return table_bytes(m, 1) + align16(kWaves1 * sizeof(WaveLds1)) + kWaves1 * map_bytes(m); }
 size_t lds2(int m) {
-  return table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2)) + kWaves2 * 2 * map_bytes(m);
+  return table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2)) + sizeof(WgList) +
+         kWaves2 * 2 * map_bytes(m);
 }
 
 template <int DV>
 hipError_t launch_dv(const ScreenArgs& a, int grid1, int grid2, hipStream_t s) {
-  switch (a.vec) {
-    case 16: hipLaunchKernelGGL((k_screen1<16, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
-    case 4: hipLaunchKernelGGL((k_screen1<4, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
-    case 1: hipLaunchKernelGGL((k_screen1<1, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !a.t2) return e;
-  switch (a.vec) {
-    case 16: hipLaunchKernelGGL((k_screen2<16, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
-    case 4: hipLaunchKernelGGL((k_screen2<4, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
-    case 1: hipLaunchKernelGGL((k_screen2<1, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
-    default: return hipErrorInvalidValue;
+  if (a.t2) {
+    switch (a.vec) {
+      case 16: hipLaunchKernelGGL((k_screen12<16, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+      case 4: hipLaunchKernelGGL((k_screen12<4, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+      case 1: hipLaunchKernelGGL((k_screen12<1, DV>), dim3(grid2), dim3(kScreen2Block), lds2(a.m), s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.vec) {
+      case 16: hipLaunchKernelGGL((k_screen1<16, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+      case 4: hipLaunchKernelGGL((k_screen1<4, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+      case 1: hipLaunchKernelGGL((k_screen1<1, DV>), dim3(grid1), dim3(kScreenBlock), lds1(a.m), s, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -838,7 +911,7 @@ int screen_blocks_per_cu(int m, int which) {
   int n = 0;
   const hipError_t e =
       which == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen1<16, 8>, kScreenBlock, lds1(m))
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen2<16, 8>, kScreen2Block, lds2(m));
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_screen12<16, 8>, kScreen2Block, lds2(m));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
