@@ -246,29 +246,31 @@ __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W
                                           const uint16_t* rows, int np, int lane, Fn fn) {
   constexpr int NM = MAG ? (DV + 3) / 4 : 1;
   for (int base = 0; base < np; base += 64 * U) {
+    // Lanes past the last pair read the last pair's data and skip it: every
+    // load is unconditional, so that all of them issue together.
     uint4 rq[U];
     uint2 jl[U];
     float4 mg[U][NM];
-    int li[U], pos[U];
+    int li[U], pos[U], c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int c = base + 64 * u + lane;
-      li[u] = -1;
-      pos[u] = 0;
-      if (c < np) {
-        li[u] = W.cmap[c];
-        pos[u] = W.cst[li[u]] + (c - W.coff[li[u]]);
-        rq[u] = a.edge_rows[pos[u]];
-        jl[u] = a.edge_col[pos[u]];
-        if constexpr (MAG) {
+      c[u] = base + 64 * u + lane;
+      li[u] = W.cmap[min(c[u], np - 1)];
+    }
 #pragma unroll
-          for (int k = 0; k < NM; ++k) mg[u][k] = a.edge_mag[2 * pos[u] + k];
-        }
+    for (int u = 0; u < U; ++u) pos[u] = W.cst[li[u]] + (min(c[u], np - 1) - W.coff[li[u]]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      rq[u] = a.edge_rows[pos[u]];
+      jl[u] = a.edge_col[pos[u]];
+      if constexpr (MAG) {
+#pragma unroll
+        for (int k = 0; k < NM; ++k) mg[u][k] = a.edge_mag[2 * pos[u] + k];
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (li[u] >= 0) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u], mg[u]);
+      if (c[u] < np) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u], mg[u]);
   }
 }
 
