@@ -125,7 +125,7 @@ struct bsd_code_s {
   bool all_pos = false;  // every prior LLR > 0 in single precision
   int32_t* s_rowptr = nullptr;
   uint4* s_edgerows = nullptr;
-  uint2* s_edgecol = nullptr;
+  uint4* s_edgecol = nullptr;
   int screen_per_cu = 1, screen2_per_cu = 1;
   int maxdeg_col = 1;
   // Batched decoding: one lane per stream the handle has been used on.
@@ -764,7 +764,6 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   sa.edge_col = c->s_edgecol;
   sa.edge_mag = ft ? reinterpret_cast<const float4*>(ft->d_pairmag) : nullptr;
   sa.row_e1min = ft ? ft->d_e1min : nullptr;
-  sa.lmask = g.lmask;
   sa.shots = a.shots;
   sa.syn = a.syn;
   sa.corr = a.corr;
@@ -1041,12 +1040,12 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     delete c;
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
-  // Screen of iteration 1: rows in CSR form (ascending columns); per edge in
-  // that order, its column's rows (original numbering, ascending) and its
-  // column with the column's prior LLR.
+  // Screen: rows in CSR form (ascending columns); per edge in that order,
+  // its column's rows (original numbering, ascending), and its column with
+  // the column's prior LLR and logical mask.
   std::vector<int32_t> srp(m + 1, 0);
   std::vector<uint16_t> ser((size_t)nnz * 8, 0xFFFFu);
-  std::vector<uint32_t> sec((size_t)nnz * 2);
+  std::vector<uint32_t> sec((size_t)nnz * 4);
   for (int e = 0; e < nnz; ++e) srp[h_rowidx[e] + 1]++;
   for (int i = 0; i < m; ++i) srp[i + 1] += srp[i];
   {
@@ -1058,8 +1057,10 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
           ser[(size_t)q * 8 + (f - h_colptr[j])] = (uint16_t)h_rowidx[f];
         uint32_t lb;
         std::memcpy(&lb, &lam[j], 4);
-        sec[(size_t)q * 2] = (uint32_t)j;
-        sec[(size_t)q * 2 + 1] = lb;
+        sec[(size_t)q * 4] = (uint32_t)j;
+        sec[(size_t)q * 4 + 1] = lb;
+        sec[(size_t)q * 4 + 2] = (uint32_t)lmask[j];
+        sec[(size_t)q * 4 + 3] = (uint32_t)(lmask[j] >> 32);
       }
   }
   c->owned = {d_diag, d_ror, d_dor, d_ci, d_ce, d_cr, d_lam, d_lm, d_l64};
@@ -1076,7 +1077,7 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
   c->s_edgerows = reinterpret_cast<uint4*>(d_ser);
-  c->s_edgecol = reinterpret_cast<uint2*>(d_sec);
+  c->s_edgecol = reinterpret_cast<uint4*>(d_sec);
   // Unrolled decoder: the CSC pointers, and each row's edges (CSC positions)
   // in ascending column order.
   {

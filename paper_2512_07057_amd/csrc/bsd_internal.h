@@ -205,12 +205,12 @@ struct ScreenArgs {
   const int32_t* row_ptr;      // [m + 1] rows (original numbering) in CSR form
   const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
                                //   ascending (0xFFFF unused)
-  const uint2* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits
+  const uint4* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits, its
+                               //   logical mask (low, high 32 bits)
   const float4* edge_mag;      // [2 nnz] CSR order: the magnitudes of eq. (1) at t = 1 on the
                                //   edge's column's edges (x_i, or y_i on the edge of the row's
                                //   least |Lambda|), in the order of edge_rows, 0 unused
   const float* row_e1min;      // [m] least E(1) the row receives for s = 0 (a lower bound)
-  const uint64_t* lmask;       // [n]
   long long shots;
   const uint8_t* syn;
   uint8_t* corr;

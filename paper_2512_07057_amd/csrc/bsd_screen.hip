@@ -81,7 +81,7 @@ struct WaveLds1 {
   int32_t set[kScreenMaxSet];          // columns with e-hat_j = 1
   int32_t nset;
   int32_t nexact;
-  int32_t pad[2];
+  uint32_t flw[2];                     // A e-hat: logical masks of the set columns, xor-ed
 };
 
 // Iteration 2 adds S2, the rows to scan and per-row message information.
@@ -249,7 +249,7 @@ __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W
     // Lanes past the last pair read the last pair's data and skip it: every
     // load is unconditional, so that all of them issue together.
     uint4 rq[U];
-    uint2 jl[U];
+    uint4 jl[U];
     float4 mg[U][NM];
     int li[U], pos[U], c[U];
 #pragma unroll
@@ -349,11 +349,14 @@ __device__ __forceinline__ void e1_all(float lam, const float (&d)[DV], float (&
   }
 }
 
-// Adds column j to e-hat: its detectors join s + H e-hat.
+// Adds column j (record jl) to e-hat: its detectors join s + H e-hat and
+// its logical mask joins A e-hat.
 template <int DV>
-__device__ __forceinline__ void set_column(WaveLds1& W, int j, const int (&r)[DV], int m) {
+__device__ __forceinline__ void set_column(WaveLds1& W, const uint4& jl, const int (&r)[DV], int m) {
   const int q = atomicAdd(&W.nset, 1);
-  if (q < kScreenMaxSet) W.set[q] = j;
+  if (q < kScreenMaxSet) W.set[q] = (int)jl.x;
+  atomicXor(&W.flw[0], jl.z);
+  atomicXor(&W.flw[1], jl.w);
 #pragma unroll
   for (int e = 0; e < DV; ++e)
     if (r[e] < m) atomicXor(&W.rbits[r[e] >> 5], 1u << (r[e] & 31));
@@ -388,7 +391,7 @@ __device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W, cons
                                           int lane) {
   constexpr int NM = (DV + 3) / 4;
   for_pairs<kUnroll2, DV, true>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq,
-                                                          const uint2& jl, const float4 (&mg)[NM]) {
+                                                          const uint4& jl, const float4 (&mg)[NM]) {
     int r[DV];
     uint32_t sb[DV];
     float d[DV];
@@ -455,7 +458,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   wave_sync();
   float gmin = kLlrMax;
   for_pairs<kUnroll2, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                               const uint2& jl, const float4 (&mg)[NM]) {
+                                                               const uint4& jl, const float4 (&mg)[NM]) {
     int r[DV];
     uint32_t sb[DV];
     bool fl[DV];
@@ -523,10 +526,11 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   if (lane == 0) {
     W.nset = 0;
     W.nexact = 0;
+    W.flw[0] = W.flw[1] = 0u;
   }
   wave_sync();
   for_pairs<kUnroll2, DV, false>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq,
-                                                              const uint2& jl, const float4 (&)[1]) {
+                                                              const uint4& jl, const float4 (&)[1]) {
     int r[DV], q[DV];
     bool in2[DV];
     float mag[DV];
@@ -559,7 +563,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
     }
     if (!(post <= 0.f)) return;
     if (exact) {
-      set_column<DV>(W, j, r, m);
+      set_column<DV>(W, jl, r, m);
       return;
     }
     const int qx = atomicAdd(&W.nexact, 1);
@@ -586,7 +590,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   if (lane < nexact) {
     const int pos = W.xpos[lane];
     const uint4 rq = a.edge_rows[pos];
-    const uint2 jl = a.edge_col[pos];
+    const uint4 jl = a.edge_col[pos];
     float4 mg[NM];
 #pragma unroll
     for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
@@ -606,7 +610,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
       const bool neg = q[e] >= 0 && ((W.rpar[q[e] >= 0 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
       post = post + (neg ? -mag[e] : mag[e]);
     }
-    if (post <= 0.f) set_column<DV>(W, j, r, m);
+    if (post <= 0.f) set_column<DV>(W, jl, r, m);
   }
   wave_sync();
   return true;
@@ -645,25 +649,16 @@ __device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* 
   }
 }
 
-// Outputs of a finished shot from W.set: corrections, logical flips
-// (A e-hat), converged flag.
+// Outputs of a finished shot from W.set and W.flw: corrections, logical
+// flips (A e-hat), converged flag.
 template <int V>
 __device__ __forceinline__ void write_shot(const ScreenArgs& a, const WaveLds1& W, long long shot,
                                            int lane) {
   const int nset = W.nset;
   const int myj = lane < nset ? W.set[lane] : -1;
-  // (the logical masks are loaded before the stores: a load issued after
-  // them would wait for them too)
-  const unsigned long long lm = myj >= 0 ? a.lmask[myj] : 0ull;
+  const uint32_t fw = W.flw[lane >= 32 ? 1 : 0];
   write_corrections<V>(a, a.corr + shot * a.n, myj, lane);
-  uint32_t lo = (uint32_t)lm, hi = (uint32_t)(lm >> 32);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    lo ^= __shfl_xor(lo, o, 64);
-    hi ^= __shfl_xor(hi, o, 64);
-  }
-  const unsigned long long fl = (unsigned long long)lo | ((unsigned long long)hi << 32);
-  if (lane < a.k) a.flips[shot * a.k + lane] = (uint8_t)((fl >> lane) & 1ull);
+  if (lane < a.k) a.flips[shot * a.k + lane] = (uint8_t)((fw >> (lane & 31)) & 1u);
   if (lane == 0) a.conv[shot] = 1;
 }
 
@@ -709,7 +704,10 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
     err |= syndrome_in(a, shot, sv, W, smap, lane);
     if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
     W.rbits[lane] = W.sbits[lane];
-    if (lane == 0) W.nset = 0;
+    if (lane == 0) {
+      W.nset = 0;
+      W.flw[0] = W.flw[1] = 0u;
+    }
     int nflip, ncand;
     const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
     if (ok) {
@@ -717,7 +715,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
       // ascending order (absent slots add 0).  The column is kept only by
       // its lowest flipped detector, so that it counts once.
       for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                                  const uint2& jl, const float4 (&mg)[NM]) {
+                                                                  const uint4& jl, const float4 (&mg)[NM]) {
         int r[DV];
         uint32_t sb[DV];
         bool fl[DV];
@@ -731,7 +729,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
 #pragma unroll
         for (int e = 0; e < DV; ++e) post = post + d[e];
         if (first_set<DV>(r, fl) == i && post <= 0.f)  // eq. (4): e-hat_j = 1
-          set_column<DV>(W, (int)jl.x, r, m);
+          set_column<DV>(W, jl, r, m);
       });
       wave_sync();
     }
@@ -794,12 +792,15 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     err |= syndrome_in(a, shot, sv, W, smap, lane);
     if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
     W.rbits[lane] = W.sbits[lane];
-    if (lane == 0) W.nset = 0;
+    if (lane == 0) {
+      W.nset = 0;
+      W.flw[0] = W.flw[1] = 0u;
+    }
     int nflip, ncand;
     const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
     if (ok) {
       for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                                  const uint2& jl, const float4 (&mg)[NM]) {
+                                                                  const uint4& jl, const float4 (&mg)[NM]) {
         int r[DV];
         uint32_t sb[DV];
         bool fl[DV];
@@ -812,7 +813,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
         float post = __uint_as_float(jl.y);
 #pragma unroll
         for (int e = 0; e < DV; ++e) post = post + d[e];
-        if (first_set<DV>(r, fl) == i && post <= 0.f) set_column<DV>(W, (int)jl.x, r, m);
+        if (first_set<DV>(r, fl) == i && post <= 0.f) set_column<DV>(W, jl, r, m);
       });
       wave_sync();
     }
