@@ -345,14 +345,17 @@ def main():
                    "lds_bytes": info["lds_bytes"]},
         "latency_us": {"p50": pct(lat_us, 50), "p99": pct(lat_us, 99), "p999": pct(lat_us, 99.9),
                        "max": float(lat_us.max()),
-                       "what": "per shot, device clock: its time in the iteration-1 screen plus, "
-                               "for a shot the screen hands on, the persistent decoder's time "
-                               "from its initial BP run to its result write"},
+                       "what": "per shot, device clock: its processing time in the screen "
+                               "(iteration 1, and iteration 2 if it needs it) plus, for a shot "
+                               "the screen hands on, the persistent decoder's time from its "
+                               "initial BP run to its result write"},
         "kernel_ms": kms,
-        "kernels": {"k_screen_ms": sms, "k_batched_ms": kms - sms,
+        "kernels": {"screen_ms": sms, "dense_ms": kms - sms,
                     "screened_shots": int(stats[-1]["screened_shots"]),
                     "screened_at_t2": int(stats[-1]["screened2_shots"]),
-                    "dense_shots": int(shots - stats[-1]["screened_shots"])},
+                    "dense_shots": int(shots - stats[-1]["screened_shots"]),
+                    "what": "screen: k_screen12 (iterations 1 and 2 of the initial run, one "
+                            "wave per shot); dense: k_batched (persistent decoder for the rest)"},
         "work_rate": {"edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
                       "bp_iterations_per_step": iters,
                       "what": "BP iterations x Tanner edges per second of kernel time; a work "
