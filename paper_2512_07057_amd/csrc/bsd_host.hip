@@ -94,7 +94,7 @@ struct FiTab {
   uint4* d_rows = nullptr;
   uint32_t* d_negbits = nullptr;
   float* d_e1min = nullptr;    // screen: least zero-syndrome E(1) per row (lowered 1 %)
-  float* d_pairmag = nullptr;  // screen: per CSR pair, the column's t = 1 magnitudes (8 slots)
+  float* d_rowxy = nullptr;    // screen: per row (and row m), x and y of eq. (1) at t = 1
   FirstIter fi{};
 };
 
@@ -248,7 +248,7 @@ void fitab_free(FiTab* t) {
   hipFree(t->d_rows);
   hipFree(t->d_negbits);
   hipFree(t->d_e1min);
-  hipFree(t->d_pairmag);
+  hipFree(t->d_rowxy);
   delete t;
 }
 
@@ -575,7 +575,7 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
   std::vector<std::vector<int>> rows(m);
   for (int e = 0; e < nnz; ++e) rows[ri[e]].push_back(e);  // ascending column = diagonal order
   std::vector<uint4> rt((size_t)m), rtab((size_t)m, make_uint4(0u, 0u, 0xFFFFFFFFu, 0u));
-  std::vector<float> t_e1min, t_pairmag;
+  std::vector<float> t_e1min, t_rowxy((size_t)2 * (m + 1), 0.f);
   std::vector<uint32_t> neg((size_t)g.nnz_pad / 32 + 1, 0u);
   for (int i = 0; i < m; ++i) {
     float m1 = kLlrMax, m2 = kLlrMax;
@@ -602,6 +602,8 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
     std::memcpy(&yb, &y, 4);
     rt[rank] = make_uint4(xb, yb, (uint32_t)argk | ((uint32_t)par << 8) | ((uint32_t)anyneg << 9), 0u);
     rtab[i] = make_uint4(xb, yb, (uint32_t)ecol[rows[i][argk]], 0u);
+    t_rowxy[2 * (size_t)i] = x;
+    t_rowxy[2 * (size_t)i + 1] = y;
   }
   // Per row, the least E(1) it receives for s = 0 (eq. (2) at t = 1 from the
   // table's x and y, in the variable phase's single-precision order): the
@@ -631,29 +633,11 @@ bsd_status build_first(bsd_code c, float alpha, const FiTab** out) {
     for (int i = 0; i < m; ++i) e1min[i] = 0.99f * e1min[i];
     t_e1min.swap(e1min);
   }
-  // Per (row, column) pair in CSR order (rows ascending, then columns): the
-  // magnitudes of the t = 1 messages on the column's edges, in CSC order --
-  // what the screen sums for the column, without a per-row lookup.
-  {
-    std::vector<int32_t> rp((size_t)m + 1, 0);
-    for (int e = 0; e < nnz; ++e) rp[ri[e] + 1]++;
-    for (int i = 0; i < m; ++i) rp[i + 1] += rp[i];
-    std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
-    t_pairmag.assign((size_t)nnz * 8, 0.f);
-    for (int j = 0; j < n; ++j)
-      for (int e = cp[j]; e < cp[j + 1]; ++e) {
-        const size_t q = (size_t)fill[ri[e]]++;
-        for (int f = cp[j]; f < cp[j + 1]; ++f) {
-          const uint4& t = rtab[ri[f]];
-          std::memcpy(&t_pairmag[q * 8 + (f - cp[j])], (int)t.z == j ? &t.y : &t.x, 4);
-        }
-      }
-  }
   FiTab* t = new (std::nothrow) FiTab;
   if (!t) return fail(BSD_ENOMEM, "host allocation failed");
   t->alpha = alpha;
   if (dev_upload(&t->d_rows, rt) != hipSuccess || dev_upload(&t->d_e1min, t_e1min) != hipSuccess ||
-      dev_upload(&t->d_pairmag, t_pairmag) != hipSuccess ||
+      dev_upload(&t->d_rowxy, t_rowxy) != hipSuccess ||
       dev_upload(&t->d_negbits, neg) != hipSuccess) {
     (void)hipGetLastError();
     fitab_free(t);
@@ -762,7 +746,7 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   sa.row_ptr = c->s_rowptr;
   sa.edge_rows = c->s_edgerows;
   sa.edge_col = c->s_edgecol;
-  sa.edge_mag = ft ? reinterpret_cast<const float4*>(ft->d_pairmag) : nullptr;
+  sa.row_xy = ft ? reinterpret_cast<const float2*>(ft->d_rowxy) : nullptr;
   sa.row_e1min = ft ? ft->d_e1min : nullptr;
   sa.shots = a.shots;
   sa.syn = a.syn;
@@ -772,7 +756,6 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   sa.lat = a.lat;
   sa.st = a.st;
   sa.list = const_cast<int32_t*>(a.shot_list);
-  sa.list2 = sa.list ? sa.list + a.shots : nullptr;
   return sa;
 }
 
@@ -808,8 +791,8 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
       hipFree(l->d_list);
       l->d_list = nullptr;
       l->list_cap = 0;
-      // the dense decoder's list, then the iteration-2 screen's
-      if (hipMalloc((void**)&l->d_list, (size_t)shots * 8) != hipSuccess) {
+      // the shots the screen hands to the dense decoder
+      if (hipMalloc((void**)&l->d_list, (size_t)shots * 4) != hipSuccess) {
         (void)hipGetLastError();
         return fail(BSD_ENOMEM, "cannot allocate the screen's shot list (%lld shots)", (long long)shots);
       }
@@ -1041,20 +1024,36 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     return fail(BSD_ENOMEM, "cannot upload the graph");
   }
   // Screen: rows in CSR form (ascending columns); per edge in that order,
-  // its column's rows (original numbering, ascending), and its column with
-  // the column's prior LLR and logical mask.
+  // its column's rows (original numbering, ascending), each flagged when the
+  // column holds that row's least |Lambda| (the first column in ascending
+  // order with the least, as in the first-iteration table), and its column
+  // with the column's prior LLR and logical mask.
   std::vector<int32_t> srp(m + 1, 0);
   std::vector<uint16_t> ser((size_t)nnz * 8, 0xFFFFu);
   std::vector<uint32_t> sec((size_t)nnz * 4);
   for (int e = 0; e < nnz; ++e) srp[h_rowidx[e] + 1]++;
   for (int i = 0; i < m; ++i) srp[i + 1] += srp[i];
   {
+    std::vector<int32_t> hold((size_t)m, -1);
+    std::vector<float> least((size_t)m, kLlrMax);
+    for (int j = 0; j < n; ++j)
+      for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+        const int i = h_rowidx[e];
+        const float a = std::fabs(lam[j]);
+        if (hold[i] < 0) hold[i] = j;
+        if (a < least[i]) {
+          least[i] = a;
+          hold[i] = j;
+        }
+      }
     std::vector<int32_t> fill(srp.begin(), srp.end() - 1);
     for (int j = 0; j < n; ++j)
       for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
         const int q = fill[h_rowidx[e]]++;
-        for (int f = h_colptr[j]; f < h_colptr[j + 1]; ++f)
-          ser[(size_t)q * 8 + (f - h_colptr[j])] = (uint16_t)h_rowidx[f];
+        for (int f = h_colptr[j]; f < h_colptr[j + 1]; ++f) {
+          const int i = h_rowidx[f];
+          ser[(size_t)q * 8 + (f - h_colptr[j])] = (uint16_t)(i | (hold[i] == j ? 0x8000 : 0));
+        }
         uint32_t lb;
         std::memcpy(&lb, &lam[j], 4);
         sec[(size_t)q * 4] = (uint32_t)j;

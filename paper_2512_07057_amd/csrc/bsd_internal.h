@@ -102,9 +102,6 @@ struct BatchState {
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
   int32_t listed;          // shots the screen handed to the dense decoder
   unsigned long long done2;  // shots the screen finished at iteration 2
-  unsigned long long screen_next;   // iteration-1 screen: shots claimed past the static ones
-  unsigned long long screen2_next;  // iteration-2 screen: list positions claimed
-  int32_t listed2;                  // shots the iteration-1 screen handed to the iteration-2 screen
   uint32_t sticky;         // errors of earlier calls on this workspace, until reported
 };
 
@@ -204,12 +201,13 @@ struct ScreenArgs {
   float alpha2;                // scaling of eq. (1) at iteration 2
   const int32_t* row_ptr;      // [m + 1] rows (original numbering) in CSR form
   const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
-                               //   ascending (0xFFFF unused)
+                               //   ascending: row in bits 0-14, bit 15 set when the column
+                               //   holds the row's least |Lambda| (0xFFFF unused)
   const uint4* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits, its
                                //   logical mask (low, high 32 bits)
-  const float4* edge_mag;      // [2 nnz] CSR order: the magnitudes of eq. (1) at t = 1 on the
-                               //   edge's column's edges (x_i, or y_i on the edge of the row's
-                               //   least |Lambda|), in the order of edge_rows, 0 unused
+  const float2* row_xy;        // [m + 1] per row, the magnitudes of eq. (1) at t = 1: x_i to
+                               //   every column but the holder of the least |Lambda|, y_i to
+                               //   that one (row m: 0, 0)
   const float* row_e1min;      // [m] least E(1) the row receives for s = 0 (a lower bound)
   long long shots;
   const uint8_t* syn;
@@ -217,10 +215,8 @@ struct ScreenArgs {
   uint8_t* flips;
   uint8_t* conv;
   uint32_t* lat;               // or NULL
-  BatchState* st;              // error, done, runs, iterations, listed, listed2
+  BatchState* st;              // error, done, done2, runs, iterations, listed
   int32_t* list;               // [shots] shots for the dense decoder
-  int32_t* list2;              // [shots] shots for iteration 2 of the screen (shot + 1; 0 until
-                               //   written; zeroed by the reset kernel)
 };
 constexpr int kScreenBlock = 512;        // iteration 1: eight shots in flight per workgroup
 constexpr int kScreen1MinWaves = 4;      // iteration 1: waves per SIMD the registers must allow

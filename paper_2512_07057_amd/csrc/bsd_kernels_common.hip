@@ -10,11 +10,6 @@ __global__ void k_batch_reset(BatchArgs a) {
   const int n = gridDim.x * blockDim.x;
   for (uint32_t q = i; q < a.work_cap; q += n) a.work_ring[q] = 0u;
   for (uint32_t q = i; q < a.ctx_cap; q += n) a.ctx_ring[q] = q < (uint32_t)a.nctx ? q + 1u : 0u;
-  // the screen's list of iteration-2 shots: entries are written once each (shot + 1)
-  if (a.shot_list) {
-    int32_t* list2 = const_cast<int32_t*>(a.shot_list) + a.shots;
-    for (long long q = i; q < a.shots; q += n) list2[q] = 0;
-  }
   if (i == 0) {
     a.st->next_shot = 0;
     a.st->done = 0;
@@ -37,9 +32,6 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->poll_token = 0;
     a.st->listed = 0;
     a.st->done2 = 0;
-    a.st->screen_next = 0;
-    a.st->screen2_next = 0;
-    a.st->listed2 = 0;
   }
 }
 

@@ -36,14 +36,16 @@
 // appended to the list that the dense persistent decoder takes its shots
 // from.
 //
-// A workgroup keeps the row pointers (and for iteration 2 each row's least
-// zero-syndrome E(1)) in LDS for the whole launch.  Each wave holds one
-// shot's syndrome as a byte per row (and for iteration 2 a byte per row
-// naming its entry of the row information), bit-vectors for listing rows,
-// row lists and (row, column) pair lists.  A column's absent row slots read
-// the byte of a row m that is always 0.  Per shot the global reads are its
-// syndrome and, per (row, column) pair, the column, its prior, its rows and
-// the magnitudes of their iteration-1 messages.
+// A workgroup keeps the row pointers, each row's two iteration-1 message
+// magnitudes (x_i, y_i) and for iteration 2 each row's least zero-syndrome
+// E(1) in LDS for the whole launch.  Each wave holds one shot's syndrome as
+// a byte per row (and for iteration 2 a byte per row naming its entry of
+// the row information), bit-vectors for listing rows, row lists and
+// (row, column) pair lists.  A column's absent row slots read the entries of
+// a row m that are always 0.  Per shot the global reads are its syndrome
+// and, per (row, column) pair, two 16-byte records: the column's rows, each
+// flagged when the column holds the row's least |Lambda| (it then receives
+// y_i), and the column with its prior and logical mask.
 #include <hip/hip_runtime.h>
 
 #include "bsd_internal.h"
@@ -108,10 +110,12 @@ static_assert(sizeof(WgList) % 16 == 0, "keeps the byte maps 16-byte aligned");
 
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// Per-workgroup tables: the row pointers, and for iteration 2 the least
-// zero-syndrome E(1) of each row (0 for row m).
+// Per-workgroup tables: the row pointers, each row's x and y of eq. (1) at
+// t = 1 (0, 0 for row m), and for iteration 2 the least zero-syndrome E(1)
+// of each row (0 for row m).
 __host__ __device__ constexpr size_t table_bytes(int m, int which) {
-  return align16(4 * (size_t)(m + 1)) + (which == 2 ? align16(4 * (size_t)(m + 1)) : 0);
+  return align16(4 * (size_t)(m + 1)) + align16(8 * (size_t)(m + 1)) +
+         (which == 2 ? align16(4 * (size_t)(m + 1)) : 0);
 }
 
 // Per-wave byte maps: the syndrome (rows 0..m), and for iteration 2 the
@@ -130,38 +134,54 @@ __device__ __forceinline__ void set_bit(uint32_t* bits, int r) {
   atomicOr(&bits[r >> 5], 1u << (r & 31));
 }
 
-// Exclusive prefix sum over the wave and the total.
+// DPP controls: shift right by n lanes within a row of 16; lane 15 of each
+// row to the next row (rows chosen by the row mask); lane 31 to rows 2, 3.
+constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Exclusive prefix sum over the wave and the total: an inclusive scan within
+// each row of 16 lanes by shifts of 1, 2, 4 and 8 (lanes shifted in from
+// outside the row add 0), then row 0's total into rows 1 and 3 and rows 0-1's
+// total into rows 2 and 3.
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total) {
+  (void)lane;
   int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  *total = __shfl(x, 63, 64);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xF, 0xF, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xF, 0xF, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xF, 0xF, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xF, 0xF, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowBcast15, 0xA, 0xF, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kRowBcast31, 0xC, 0xF, false);
+  *total = __builtin_amdgcn_readlane(x, 63);
   return x - v;
 }
 
+// Least value over the wave (lane 63 ends with the least of all lanes; lanes
+// shifted in from outside a row, and rows the masks leave out, keep their
+// own value).
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+  int x = __float_as_int(v);
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowShr + 1, 0xF, 0xF, false))));
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowShr + 2, 0xF, 0xF, false))));
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowShr + 4, 0xF, 0xF, false))));
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowShr + 8, 0xF, 0xF, false))));
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowBcast15, 0xA, 0xF, false))));
+  x = __float_as_int(fminf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, kRowBcast31, 0xC, 0xF, false))));
+  return __int_as_float(__builtin_amdgcn_readlane(x, 63));
 }
 
-// Lane 0's 64-bit value in every lane.
-__device__ __forceinline__ unsigned long long bcast64(unsigned long long v) {
-  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, 0, 64);
-  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), 0, 64);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
+// A shot's syndrome (m / 8 rows of 8 bytes per lane-slot), read once: non-temporal.
 __device__ __forceinline__ void load_syn_regs(const ScreenArgs& a, long long shot, int lane,
                                               uint2 (&v)[kSynRegs]) {
   const uint2* s8 = reinterpret_cast<const uint2*>(a.syn + shot * a.m);
 #pragma unroll
   for (int u = 0; u < kSynRegs; ++u) {
     const int d = lane + 64 * u;
-    v[u] = d < (a.m >> 3) ? s8[d] : make_uint2(0u, 0u);
+    if (d < (a.m >> 3)) {
+      const unsigned long long x = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(s8) + d);
+      v[u] = make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+    } else {
+      v[u] = make_uint2(0u, 0u);
+    }
   }
 }
 
@@ -238,19 +258,16 @@ __device__ __forceinline__ int list_pairs(const int32_t* rptr, const uint16_t* r
 }
 
 // fn(listed row index, row, CSR position, column's rows, (column, Lambda
-// bits), the column's iteration-1 message magnitudes) for every pair of the
-// listed rows, U pairs per lane in flight.  The magnitudes (MAG, 4 per
-// float4) are loaded only when asked for.
-template <int U, int DV, bool MAG, class Fn>
+// bits, logical mask)) for every pair of the listed rows, U pairs per lane
+// in flight.
+template <int U, class Fn>
 __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W,
                                           const uint16_t* rows, int np, int lane, Fn fn) {
-  constexpr int NM = MAG ? (DV + 3) / 4 : 1;
   for (int base = 0; base < np; base += 64 * U) {
     // Lanes past the last pair read the last pair's data and skip it: every
     // load is unconditional, so that all of them issue together.
     uint4 rq[U];
     uint4 jl[U];
-    float4 mg[U][NM];
     int li[U], pos[U], c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -263,22 +280,11 @@ __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W
     for (int u = 0; u < U; ++u) {
       rq[u] = a.edge_rows[pos[u]];
       jl[u] = a.edge_col[pos[u]];
-      if constexpr (MAG) {
-#pragma unroll
-        for (int k = 0; k < NM; ++k) mg[u][k] = a.edge_mag[2 * pos[u] + k];
-      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (c[u] < np) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u], mg[u]);
+      if (c[u] < np) fn(li[u], (int)rows[li[u]], pos[u], rq[u], jl[u]);
   }
-}
-
-// Magnitude of slot e of a column's iteration-1 messages.
-template <int NM>
-__device__ __forceinline__ float mag_at(const float4 (&mg)[NM], int e) {
-  const float4 v = mg[e >> 2];
-  return (e & 3) == 0 ? v.x : (e & 3) == 1 ? v.y : (e & 3) == 2 ? v.z : v.w;
 }
 
 // The column's rows in slot order (ascending); absent slots give row m.
@@ -287,7 +293,7 @@ __device__ __forceinline__ void col_rows(const uint4& rq, int m, int (&r)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
     const uint32_t w = e < 2 ? rq.x : e < 4 ? rq.y : e < 6 ? rq.z : rq.w;
-    r[e] = min((int)((w >> (16 * (e & 1))) & 0xFFFFu), m);
+    r[e] = min((int)((w >> (16 * (e & 1))) & 0x7FFFu), m);
   }
 }
 
@@ -308,14 +314,17 @@ __device__ __forceinline__ int first_set(const int (&r)[DV], const bool (&f)[DV]
 }
 
 // Eq. (1) at t = 1 on the edges of a column: the magnitude of the row's
-// message (x, or y on the edge of its least |Lambda|; 0 on absent slots),
-// negative when s_i = 1.
-template <int DV, int NM>
-__device__ __forceinline__ void col_d1(const uint32_t (&sb)[DV], const float4 (&mg)[NM],
-                                       float (&d)[DV]) {
+// message (xy[row].x, or .y when the slot's flag says the column holds the
+// row's least |Lambda|; row m gives 0 on absent slots), negative when
+// s_i = 1.
+template <int DV>
+__device__ __forceinline__ void col_d1(const float2* xy, const uint4& rq, const int (&r)[DV],
+                                       const uint32_t (&sb)[DV], float (&d)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
-    const float mag = mag_at<NM>(mg, e);
+    const uint32_t w = e < 2 ? rq.x : e < 4 ? rq.y : e < 6 ? rq.z : rq.w;
+    const float2 v = xy[r[e]];
+    const float mag = (w >> (16 * (e & 1) + 15)) & 1u ? v.y : v.x;
     d[e] = sb[e] ? -mag : mag;
   }
 }
@@ -386,18 +395,16 @@ __device__ __forceinline__ void row_info_add(WaveLds2& W, int q, float v, int j)
 // Row information of the listed rows (entry imap[row] - 1), E(1) formed
 // exactly on every edge of each row.
 template <int DV>
-__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap,
-                                          const uint8_t* imap, const uint16_t* rows, int np,
-                                          int lane) {
-  constexpr int NM = (DV + 3) / 4;
-  for_pairs<kUnroll2, DV, true>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq,
-                                                          const uint4& jl, const float4 (&mg)[NM]) {
+__device__ __forceinline__ void scan_rows(const ScreenArgs& a, WaveLds2& W, const float2* xy,
+                                          const uint8_t* smap, const uint8_t* imap,
+                                          const uint16_t* rows, int np, int lane) {
+  for_pairs<kUnroll2>(a, W, rows, np, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
     int r[DV];
     uint32_t sb[DV];
     float d[DV];
     col_rows<DV>(rq, a.m, r);
     col_map<DV>(smap, r, sb);
-    col_d1<DV, NM>(sb, mg, d);
+    col_d1<DV>(xy, rq, r, sb, d);
     int es = 0;
 #pragma unroll
     for (int e = 0; e < DV; ++e) es = r[e] == i ? e : es;
@@ -440,9 +447,9 @@ __device__ __forceinline__ void d2_slots(const WaveLds2& W, const uint8_t* imap,
 // all 0).  Leaves e-hat(2) in W.set and s + H e-hat(2) in W.rbits; returns
 // false when a list overflowed (the shot then goes to the dense decoder).
 template <int DV>
-__device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap, uint8_t* imap,
-                           const float* e1min, const int32_t* rptr, int nflip, int ncand, int lane) {
-  constexpr int NM = (DV + 3) / 4;
+__device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, const uint8_t* smap,
+                           uint8_t* imap, const float* e1min, const int32_t* rptr, int nflip,
+                           int ncand, int lane) {
   const int words = a.words_m, m = a.m;
   const float alpha = a.alpha2;
   // E(1) on every edge of the columns of flipped detectors.  Rows receiving
@@ -457,8 +464,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   }
   wave_sync();
   float gmin = kLlrMax;
-  for_pairs<kUnroll2, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                               const uint4& jl, const float4 (&mg)[NM]) {
+  for_pairs<kUnroll2>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
     int r[DV];
     uint32_t sb[DV];
     bool fl[DV];
@@ -469,7 +475,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
 #pragma unroll
     for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
     if (first_set<DV>(r, fl) != i) return;  // the column's lowest flipped row takes it
-    col_d1<DV, NM>(sb, mg, d);
+    col_d1<DV>(xy, rq, r, sb, d);
     e1_all<DV>(__uint_as_float(jl.y), d, E);
 #pragma unroll
     for (int e = 0; e < DV; ++e) {
@@ -512,7 +518,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   if (lane < nn) init_info(W, (int)imap[W.xrows[lane]] - 1, 0u);
   const int npn = list_pairs(rptr, W.xrows, nn, W, lane);
   if (npn < 0) return false;
-  scan_rows<DV>(a, W, smap, imap, W.xrows, npn, lane);
+  scan_rows<DV>(a, W, xy, smap, imap, W.xrows, npn, lane);
   const int np = list_pairs(rptr, W.rows, ns2, W, lane);
   if (np < 0) return false;
 
@@ -529,8 +535,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
     W.flw[0] = W.flw[1] = 0u;
   }
   wave_sync();
-  for_pairs<kUnroll2, DV, false>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq,
-                                                              const uint4& jl, const float4 (&)[1]) {
+  for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint4& jl) {
     int r[DV], q[DV];
     bool in2[DV];
     float mag[DV];
@@ -545,13 +550,10 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
 #pragma unroll
     for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
     if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
-    float4 mg[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
     uint32_t sb[DV];
     float d[DV], E[DV];
     col_map<DV>(smap, r, sb);
-    col_d1<DV, NM>(sb, mg, d);
+    col_d1<DV>(xy, rq, r, sb, d);
     e1_all<DV>(lam, d, E);
     float post = lam;
     bool exact = true;
@@ -586,14 +588,11 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
   }
   const int npx = list_pairs(rptr, W.xrows, nx, W, lane);
   if (npx < 0) return false;
-  scan_rows<DV>(a, W, smap, imap, W.xrows, npx, lane);
+  scan_rows<DV>(a, W, xy, smap, imap, W.xrows, npx, lane);
   if (lane < nexact) {
     const int pos = W.xpos[lane];
     const uint4 rq = a.edge_rows[pos];
     const uint4 jl = a.edge_col[pos];
-    float4 mg[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k) mg[k] = a.edge_mag[2 * pos + k];
     int r[DV], q[DV];
     uint32_t sb[DV];
     float d[DV], E[DV], mag[DV];
@@ -601,7 +600,7 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
     col_rows<DV>(rq, m, r);
     d2_slots<DV>(W, imap, e1min, r, j, alpha, gdmin, true, q, mag);
     col_map<DV>(smap, r, sb);
-    col_d1<DV, NM>(sb, mg, d);
+    col_d1<DV>(xy, rq, r, sb, d);
     const float lam = __uint_as_float(jl.y);
     e1_all<DV>(lam, d, E);
     float post = lam;
@@ -617,7 +616,9 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const uint8_t* smap
 }
 
 // e-hat as bytes, V per store: lane c of each pass of 64 stores writes chunk
-// c; one ballot finds the set columns whose chunks fall in the pass.
+// c; one ballot finds the set columns whose chunks fall in the pass.  The
+// 16-byte stores are non-temporal: the corrections stream past the L2, which
+// keeps the per-pair records that every shot gathers.
 // `myj`: the lane's entry of the set, or -1.
 template <int V>
 __device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* row, int myj,
@@ -631,7 +632,7 @@ __device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* 
     while (mk) {
       const int q = __builtin_ctzll(mk);
       mk &= mk - 1ull;
-      const int j = __shfl(myj, q, 64);
+      const int j = __builtin_amdgcn_readlane(myj, q);
       const uint32_t b = j / V == c ? (V == 1 ? 1u : 1u << (8 * (j & 3))) : 0u;
       const int wi = V == 16 ? (j >> 2) & 3 : 0;  // word of the chunk
 #pragma unroll
@@ -639,7 +640,9 @@ __device__ __forceinline__ void write_corrections(const ScreenArgs& a, uint8_t* 
     }
     if (c < nchunk) {
       if constexpr (V == 16) {
-        reinterpret_cast<uint4*>(row)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 v = {w[0], w[1], w[2], w[3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(row) + c);
       } else if constexpr (V == 4) {
         reinterpret_cast<uint32_t*>(row)[c] = w[0];
       } else {
@@ -683,11 +686,14 @@ __device__ __forceinline__ bool flipped_pairs(const ScreenArgs& a, WaveLds1& W, 
 template <int V, int DV>
 __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
-  constexpr int NM = (DV + 3) / 4;
   const int m = a.m;
   int32_t* rptr = reinterpret_cast<int32_t*>(sm);
+  float2* xy = reinterpret_cast<float2*>(sm + align16(4 * (size_t)(m + 1)));
   WaveLds1* wl = reinterpret_cast<WaveLds1*>(sm + table_bytes(m, 1));
-  for (int i = threadIdx.x; i <= m; i += kScreenBlock) rptr[i] = a.row_ptr[i];
+  for (int i = threadIdx.x; i <= m; i += kScreenBlock) {
+    rptr[i] = a.row_ptr[i];
+    xy[i] = a.row_xy[i];
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   WaveLds1& W = wl[wv];
   uint8_t* smap = reinterpret_cast<uint8_t*>(sm + table_bytes(m, 1) + align16(kWaves1 * sizeof(WaveLds1))) +
@@ -714,8 +720,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
       // Eq. (3) at t = 1: Lambda_j, then the messages of the rows in
       // ascending order (absent slots add 0).  The column is kept only by
       // its lowest flipped detector, so that it counts once.
-      for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                                  const uint4& jl, const float4 (&mg)[NM]) {
+      for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
         int r[DV];
         uint32_t sb[DV];
         bool fl[DV];
@@ -724,7 +729,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
         col_map<DV>(smap, r, sb);
 #pragma unroll
         for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
-        col_d1<DV, NM>(sb, mg, d);
+        col_d1<DV>(xy, rq, r, sb, d);
         float post = __uint_as_float(jl.y);
 #pragma unroll
         for (int e = 0; e < DV; ++e) post = post + d[e];
@@ -764,14 +769,15 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
 template <int V, int DV>
 __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(ScreenArgs a) {
   extern __shared__ __align__(16) char sm[];
-  constexpr int NM = (DV + 3) / 4;
   const int m = a.m;
   int32_t* rptr = reinterpret_cast<int32_t*>(sm);
-  float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(m + 1)));
+  float2* xy = reinterpret_cast<float2*>(sm + align16(4 * (size_t)(m + 1)));
+  float* e1min = reinterpret_cast<float*>(sm + align16(4 * (size_t)(m + 1)) + align16(8 * (size_t)(m + 1)));
   WaveLds2* wl = reinterpret_cast<WaveLds2*>(sm + table_bytes(m, 2));
   WgList* gl = reinterpret_cast<WgList*>(sm + table_bytes(m, 2) + align16(kWaves2 * sizeof(WaveLds2)));
   for (int i = threadIdx.x; i <= m; i += kScreen2Block) {
     rptr[i] = a.row_ptr[i];
+    xy[i] = a.row_xy[i];
     e1min[i] = i < m ? a.row_e1min[i] : 0.f;  // (row m: absent slots, bound 0)
   }
   for (int i = threadIdx.x; i < kWgList; i += kScreen2Block) gl->shot[i] = 0;
@@ -799,8 +805,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     int nflip, ncand;
     const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
     if (ok) {
-      for_pairs<kUnroll, DV, true>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq,
-                                                                  const uint4& jl, const float4 (&mg)[NM]) {
+      for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
         int r[DV];
         uint32_t sb[DV];
         bool fl[DV];
@@ -809,7 +814,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
         col_map<DV>(smap, r, sb);
 #pragma unroll
         for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
-        col_d1<DV, NM>(sb, mg, d);
+        col_d1<DV>(xy, rq, r, sb, d);
         float post = __uint_as_float(jl.y);
 #pragma unroll
         for (int e = 0; e < DV; ++e) post = post + d[e];
@@ -852,7 +857,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
         __builtin_amdgcn_s_sleep(4);
       }
     }
-    s2 = __shfl(s2, 0, 64);
+    s2 = __builtin_amdgcn_readfirstlane(s2);
     if (s2 < 0) break;
     if (a.syn8) load_syn_regs(a, s2, lane, sv);
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
@@ -861,7 +866,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     syndrome_in(a, s2, sv, W, smap, lane);
     int nflip, ncand;
     bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
-    ok = ok && iteration2<DV>(a, W, smap, imap, e1min, rptr, nflip, ncand, lane) &&
+    ok = ok && iteration2<DV>(a, W, xy, smap, imap, e1min, rptr, nflip, ncand, lane) &&
          W.nset <= kScreenMaxSet && __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
     if (ok) {
       write_shot<V>(a, W, s2, lane);
