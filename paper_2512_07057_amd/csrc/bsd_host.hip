@@ -732,6 +732,7 @@ ScreenArgs screen_args(const bsd_code c, const bsd_params* p, const BatchArgs& a
   // Iteration 2 as well when the initial run has one; its scaling is the
   // schedule's second entry (the last, if shorter) or alpha.
   sa.t2 = (p->initial_iters >= 2 && !(p->flags & BSD_FLAG_NO_SCREEN2)) ? 1 : 0;
+  sa.single1 = first_alpha(c, p) <= 1.0f ? 1 : 0;
   sa.alpha2 = (a.alpha_sched && !c->asched.empty())
                   ? c->asched[std::min<size_t>(2, c->asched.size()) - 1]
                   : a.alpha;
@@ -1035,24 +1036,46 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   for (int i = 0; i < m; ++i) srp[i + 1] += srp[i];
   {
     std::vector<int32_t> hold((size_t)m, -1);
-    std::vector<float> least((size_t)m, kLlrMax);
+    std::vector<float> least((size_t)m, kLlrMax), second((size_t)m, kLlrMax);
     for (int j = 0; j < n; ++j)
       for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
         const int i = h_rowidx[e];
         const float a = std::fabs(lam[j]);
         if (hold[i] < 0) hold[i] = j;
+        second[i] = std::max(least[i], std::min(second[i], a));
         if (a < least[i]) {
           least[i] = a;
           hold[i] = j;
         }
       }
+    // Whether one flipped detector alone can make column j decide 1 at t = 1
+    // for some alpha <= 1: with row f flipped the posterior is Lambda_j +
+    // alpha (b - a), a the magnitude base f sends (its least |Lambda|, or
+    // its second least to the holder) and b the sum of the others', so it
+    // stays at least Lambda_j + min(0, b - a).  A margin far above the
+    // rounding of the single-precision sum keeps the answer on the safe side.
+    std::vector<uint8_t> single((size_t)n, 0);
+    for (int j = 0; j < n; ++j) {
+      double tot = 0.0;
+      for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+        const int i = h_rowidx[e];
+        tot += hold[i] == j ? second[i] : least[i];
+      }
+      for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
+        const int i = h_rowidx[e];
+        const double a = hold[i] == j ? second[i] : least[i];
+        const double lo = (double)lam[j] + std::min(0.0, (tot - a) - a);
+        if (lo <= 1e-3 * ((double)std::fabs(lam[j]) + tot)) single[j] = 1;
+      }
+    }
     std::vector<int32_t> fill(srp.begin(), srp.end() - 1);
     for (int j = 0; j < n; ++j)
       for (int e = h_colptr[j]; e < h_colptr[j + 1]; ++e) {
         const int q = fill[h_rowidx[e]]++;
         for (int f = h_colptr[j]; f < h_colptr[j + 1]; ++f) {
           const int i = h_rowidx[f];
-          ser[(size_t)q * 8 + (f - h_colptr[j])] = (uint16_t)(i | (hold[i] == j ? 0x8000 : 0));
+          ser[(size_t)q * 8 + (f - h_colptr[j])] =
+              (uint16_t)(i | (hold[i] == j ? 0x8000 : 0) | (f == h_colptr[j] && single[j] ? 0x4000 : 0));
         }
         uint32_t lb;
         std::memcpy(&lb, &lam[j], 4);

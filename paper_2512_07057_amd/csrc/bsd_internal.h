@@ -198,11 +198,14 @@ struct ScreenArgs {
   int32_t syn8;                // 1: m % 8 == 0 and the syndromes are 8-byte aligned
   int32_t maxdeg_col;          // largest column degree (1..8)
   int32_t t2;                  // 1: also screen iteration 2 (initial_iters >= 2)
+  int32_t single1;             // 1: iteration 1's alpha <= 1, so bit 14 of edge_rows holds
   float alpha2;                // scaling of eq. (1) at iteration 2
   const int32_t* row_ptr;      // [m + 1] rows (original numbering) in CSR form
   const uint4* edge_rows;      // [nnz] CSR order: rows of the edge's column, 16 bits each,
-                               //   ascending: row in bits 0-14, bit 15 set when the column
-                               //   holds the row's least |Lambda| (0xFFFF unused)
+                               //   ascending: row in bits 0-11, bit 15 set when the column
+                               //   holds the row's least |Lambda| (0xFFFF unused); bit 14 of
+                               //   the first slot set when one detector alone may decide the
+                               //   column (for alpha <= 1)
   const uint4* edge_col;       // [nnz] CSR order: the edge's column, its Lambda bits, its
                                //   logical mask (low, high 32 bits)
   const float2* row_xy;        // [m + 1] per row, the magnitudes of eq. (1) at t = 1: x_i to

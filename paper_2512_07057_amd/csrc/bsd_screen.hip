@@ -70,6 +70,7 @@ constexpr int kMaxRows = kScreenMaxFlipped;   // rows of a pair list (flipped ro
 constexpr int kMaxX = 32;                     // S2 rows that did not flip; rows scanned for exact decisions
 constexpr int kMaxExact = 32;                 // columns decided by exact messages at t = 2
 constexpr int kInfo = kMaxRows + kMaxX;       // row info entries: S2 by rank, then scanned rows
+constexpr int kMaxHeavy = 64;                 // columns whose t = 2 bound is not positive
 
 // One shot's iteration 1: syndrome and residual bits, the flipped rows and
 // their (row, column) pairs, the set decisions.
@@ -84,6 +85,8 @@ struct WaveLds1 {
   int32_t nset;
   int32_t nexact;
   uint32_t flw[2];                     // A e-hat: logical masks of the set columns, xor-ed
+  int32_t hpos[kMaxHeavy];             // queued columns (CSR positions) for a full evaluation
+  int32_t nheavy;
 };
 
 // Iteration 2 adds S2, the rows to scan and per-row message information.
@@ -258,9 +261,9 @@ __device__ __forceinline__ int list_pairs(const int32_t* rptr, const uint16_t* r
 }
 
 // fn(listed row index, row, CSR position, column's rows, (column, Lambda
-// bits, logical mask)) for every pair of the listed rows, U pairs per lane
-// in flight.
-template <int U, class Fn>
+// bits, logical mask); zeros unless J) for every pair of the listed rows,
+// U pairs per lane in flight.
+template <int U, bool J = true, class Fn>
 __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W,
                                           const uint16_t* rows, int np, int lane, Fn fn) {
   for (int base = 0; base < np; base += 64 * U) {
@@ -279,7 +282,7 @@ __device__ __forceinline__ void for_pairs(const ScreenArgs& a, const WaveLds1& W
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       rq[u] = a.edge_rows[pos[u]];
-      jl[u] = a.edge_col[pos[u]];
+      jl[u] = J ? a.edge_col[pos[u]] : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -293,7 +296,7 @@ __device__ __forceinline__ void col_rows(const uint4& rq, int m, int (&r)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
     const uint32_t w = e < 2 ? rq.x : e < 4 ? rq.y : e < 6 ? rq.z : rq.w;
-    r[e] = min((int)((w >> (16 * (e & 1))) & 0x7FFFu), m);
+    r[e] = min((int)((w >> (16 * (e & 1))) & 0xFFFu), m);
   }
 }
 
@@ -371,6 +374,77 @@ __device__ __forceinline__ void set_column(WaveLds1& W, const uint4& jl, const i
     if (r[e] < m) atomicXor(&W.rbits[r[e] >> 5], 1u << (r[e] & 31));
 }
 
+// Eqs. (3)-(4) at t = 1 for the columns of the flipped rows (W.rows, their
+// `ncand` pairs in W.cmap / cst / coff): Lambda_j, then the messages of the
+// column's rows in ascending order (absent slots add 0), summed in single
+// precision as the dense variable phase does; each column is decided by its
+// lowest flipped row only, so that it counts once.  When iteration 1's
+// alpha is at most 1 a first pass reads only the columns' rows: a column
+// with one flipped row whose record says that one detector cannot decide it
+// has a positive posterior, and the others are queued and summed in full,
+// one per lane.  More than kMaxHeavy queued columns: the full pass instead.
+template <int DV>
+__device__ __forceinline__ void iteration1(const ScreenArgs& a, WaveLds1& W, const float2* xy,
+                                           const uint8_t* smap, int ncand, int lane) {
+  const int m = a.m;
+  auto decide = [&](const uint4& rq, const uint4& jl, const int (&r)[DV], const uint32_t (&sb)[DV]) {
+    float d[DV];
+    col_d1<DV>(xy, rq, r, sb, d);
+    float post = __uint_as_float(jl.y);
+#pragma unroll
+    for (int e = 0; e < DV; ++e) post = post + d[e];
+    if (post <= 0.f) set_column<DV>(W, jl, r, m);  // eq. (4): e-hat_j = 1
+  };
+  if (a.single1) {
+    if (lane == 0) W.nheavy = 0;
+    wave_sync();
+    for_pairs<kUnroll, false>(a, W, W.rows, ncand, lane, [&](int, int i, int pos, const uint4& rq, const uint4&) {
+      int r[DV];
+      uint32_t sb[DV];
+      bool fl[DV];
+      col_rows<DV>(rq, m, r);
+      col_map<DV>(smap, r, sb);
+      int nf = 0;
+#pragma unroll
+      for (int e = 0; e < DV; ++e) {
+        fl[e] = sb[e] != 0u;
+        nf += fl[e] ? 1 : 0;
+      }
+      if (first_set<DV>(r, fl) != i) return;
+      if (nf < 2 && !((rq.x >> 14) & 1u)) return;
+      const int q = atomicAdd(&W.nheavy, 1);
+      if (q < kMaxHeavy) W.hpos[q] = pos;
+    });
+    wave_sync();
+    const int nq = W.nheavy;
+    if (nq <= kMaxHeavy) {
+      if (lane < nq) {
+        const int pos = W.hpos[lane];
+        const uint4 rq = a.edge_rows[pos];
+        const uint4 jl = a.edge_col[pos];
+        int r[DV];
+        uint32_t sb[DV];
+        col_rows<DV>(rq, m, r);
+        col_map<DV>(smap, r, sb);
+        decide(rq, jl, r, sb);
+      }
+      wave_sync();
+      return;
+    }
+  }
+  for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
+    int r[DV];
+    uint32_t sb[DV];
+    bool fl[DV];
+    col_rows<DV>(rq, m, r);
+    col_map<DV>(smap, r, sb);
+#pragma unroll
+    for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
+    if (first_set<DV>(r, fl) == i) decide(rq, jl, r, sb);
+  });
+  wave_sync();
+}
+
 // Row information entry q: the message bound (the check phase's starting
 // least values) and s_i.
 __device__ __forceinline__ void init_info(WaveLds2& W, int q, uint32_t s) {
@@ -424,22 +498,39 @@ __device__ __forceinline__ float d2_mag(const WaveLds2& W, int q, int j, float a
   return fminf(alpha * mm, kLlrMax);
 }
 
-// Per slot of a column next to S2: the row's information entry (-1 outside
-// S2 and, with `scanned`, the scanned rows), and the magnitude of its t = 2
-// message to column j (those rows) or a lower bound of it (other rows: 0 on
-// absent slots).
+// Per slot of a column: the row's information entry (-1 outside S2 and,
+// with `scanned`, the scanned rows).
 template <int DV>
-__device__ __forceinline__ void d2_slots(const WaveLds2& W, const uint8_t* imap, const float* e1min,
-                                         const int (&r)[DV], int j, float alpha, float gdmin,
-                                         bool scanned, int (&q)[DV], float (&mag)[DV]) {
+__device__ __forceinline__ void d2_rows(const uint8_t* imap, const int (&r)[DV], bool scanned,
+                                        int (&q)[DV]) {
 #pragma unroll
   for (int e = 0; e < DV; ++e) {
     const int v = (int)imap[r[e]] - 1;
     q[e] = (v >= 0 && (scanned || v < kMaxRows)) ? v : -1;
+  }
+}
+
+// Per slot of a column next to S2 (entries q from d2_rows): the magnitude of
+// its t = 2 message to column j (rows with an entry) or a lower bound of it
+// (other rows: 0 on absent slots).
+template <int DV>
+__device__ __forceinline__ void d2_mags(const WaveLds2& W, const float* e1min, const int (&r)[DV],
+                                        const int (&q)[DV], int j, float alpha, float gdmin,
+                                        float (&mag)[DV]) {
+#pragma unroll
+  for (int e = 0; e < DV; ++e) {
     const float lb = fminf(alpha * fminf(e1min[r[e]], gdmin), kLlrMax);
     const float mm = d2_mag(W, q[e] >= 0 ? q[e] : 0, j, alpha);
     mag[e] = q[e] >= 0 ? mm : lb;
   }
+}
+
+template <int DV>
+__device__ __forceinline__ void d2_slots(const WaveLds2& W, const uint8_t* imap, const float* e1min,
+                                         const int (&r)[DV], int j, float alpha, float gdmin,
+                                         bool scanned, int (&q)[DV], float (&mag)[DV]) {
+  d2_rows<DV>(imap, r, scanned, q);
+  d2_mags<DV>(W, e1min, r, q, j, alpha, gdmin, mag);
 }
 
 // Iteration 2 of a shot whose iteration 1 did not converge (W.rows holds its
@@ -523,15 +614,20 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
   if (np < 0) return false;
 
   // Posteriors (eq. (3)) of the columns next to S2, each taken by its lowest
-  // S2 row: first with every S2 message taken negative, then with the S2
-  // messages exact.  A column whose bounded posterior is not positive and
-  // that used a bound for a row outside S2 is listed, and those rows are
-  // marked for a scan.
+  // S2 row: first with every S2 message taken negative; the columns this
+  // leaves open are queued and then taken one per lane with the S2 messages
+  // exact (so that the pass over all pairs stays short and uniform; with
+  // more than kMaxHeavy of them the pass runs again and takes them as it
+  // finds them).  A
+  // column whose bounded posterior is still not positive and that used a
+  // bound for a row outside S2 is listed, and those rows are marked for a
+  // scan.
   W.rbits[lane] = W.sbits[lane];
   W.xbits[lane] = 0u;
   if (lane == 0) {
     W.nset = 0;
     W.nexact = 0;
+    W.nheavy = 0;
     W.flw[0] = W.flw[1] = 0u;
   }
   wave_sync();
@@ -539,19 +635,27 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
     int r[DV], q[DV];
     bool in2[DV];
     float mag[DV];
-    const int j = (int)jl.x;
     col_rows<DV>(rq, m, r);
-    d2_slots<DV>(W, imap, e1min, r, j, alpha, gdmin, false, q, mag);
+    d2_rows<DV>(imap, r, false, q);
 #pragma unroll
     for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
     if (first_set<DV>(r, in2) != i) return;
-    const float lam = __uint_as_float(jl.y);
-    float lb = lam;
+    d2_mags<DV>(W, e1min, r, q, (int)jl.x, alpha, gdmin, mag);
+    float lb = __uint_as_float(jl.y);
 #pragma unroll
     for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
     if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
+    const int qh = atomicAdd(&W.nheavy, 1);
+    if (qh < kMaxHeavy) W.hpos[qh] = pos;
+  });
+  wave_sync();
+  // A column left open by the bound: the S2 messages exact (the sign of each
+  // from its row's parity and the sign of E(1) on the edge).
+  auto open_column = [&](int pos, const uint4& rq, const uint4& jl, const int (&r)[DV],
+                         const int (&q)[DV], const float (&mag)[DV]) {
     uint32_t sb[DV];
     float d[DV], E[DV];
+    const float lam = __uint_as_float(jl.y);
     col_map<DV>(smap, r, sb);
     col_d1<DV>(xy, rq, r, sb, d);
     e1_all<DV>(lam, d, E);
@@ -559,8 +663,9 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
     bool exact = true;
 #pragma unroll
     for (int e = 0; e < DV; ++e) {
-      const bool neg = in2[e] && ((W.rpar[in2[e] ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
-      exact = exact && (in2[e] || r[e] >= m);
+      const bool in2 = q[e] >= 0;
+      const bool neg = in2 && ((W.rpar[in2 ? q[e] : 0] & 1u) ^ (__float_as_uint(E[e]) >> 31));
+      exact = exact && (in2 || r[e] >= m);
       post = post + (neg ? -mag[e] : mag[e]);
     }
     if (!(post <= 0.f)) return;
@@ -572,8 +677,37 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
     if (qx < kMaxExact) W.xpos[qx] = pos;
 #pragma unroll
     for (int e = 0; e < DV; ++e)
-      if (r[e] < m && !in2[e]) set_bit(W.xbits, r[e]);
-  });
+      if (r[e] < m && q[e] < 0) set_bit(W.xbits, r[e]);
+  };
+  if (W.nheavy <= kMaxHeavy) {
+    if (lane < W.nheavy) {
+      const int pos = W.hpos[lane];
+      const uint4 rq = a.edge_rows[pos];
+      const uint4 jl = a.edge_col[pos];
+      int r[DV], q[DV];
+      float mag[DV];
+      col_rows<DV>(rq, m, r);
+      d2_slots<DV>(W, imap, e1min, r, (int)jl.x, alpha, gdmin, false, q, mag);
+      open_column(pos, rq, jl, r, q, mag);
+    }
+  } else {
+    // (too many to queue: the pass again, open columns taken at once)
+    for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint4& jl) {
+      int r[DV], q[DV];
+      bool in2[DV];
+      float mag[DV];
+      col_rows<DV>(rq, m, r);
+      d2_rows<DV>(imap, r, false, q);
+#pragma unroll
+      for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
+      if (first_set<DV>(r, in2) != i) return;
+      d2_mags<DV>(W, e1min, r, q, (int)jl.x, alpha, gdmin, mag);
+      float lb = __uint_as_float(jl.y);
+#pragma unroll
+      for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
+      if (lb <= 0.f) open_column(pos, rq, jl, r, q, mag);
+    });
+  }
   wave_sync();
   const int nexact = W.nexact;
   if (nexact == 0) return true;
@@ -716,28 +850,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
     }
     int nflip, ncand;
     const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
-    if (ok) {
-      // Eq. (3) at t = 1: Lambda_j, then the messages of the rows in
-      // ascending order (absent slots add 0).  The column is kept only by
-      // its lowest flipped detector, so that it counts once.
-      for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
-        int r[DV];
-        uint32_t sb[DV];
-        bool fl[DV];
-        float d[DV];
-        col_rows<DV>(rq, m, r);
-        col_map<DV>(smap, r, sb);
-#pragma unroll
-        for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
-        col_d1<DV>(xy, rq, r, sb, d);
-        float post = __uint_as_float(jl.y);
-#pragma unroll
-        for (int e = 0; e < DV; ++e) post = post + d[e];
-        if (first_set<DV>(r, fl) == i && post <= 0.f)  // eq. (4): e-hat_j = 1
-          set_column<DV>(W, jl, r, m);
-      });
-      wave_sync();
-    }
+    if (ok) iteration1<DV>(a, W, xy, smap, ncand, lane);
     // Stopping rule: s + H e-hat = 0.
     const bool conv = ok && W.nset <= kScreenMaxSet &&
                       __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
@@ -804,24 +917,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     }
     int nflip, ncand;
     const bool ok = flipped_pairs(a, W, rptr, lane, &nflip, &ncand);
-    if (ok) {
-      for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
-        int r[DV];
-        uint32_t sb[DV];
-        bool fl[DV];
-        float d[DV];
-        col_rows<DV>(rq, m, r);
-        col_map<DV>(smap, r, sb);
-#pragma unroll
-        for (int e = 0; e < DV; ++e) fl[e] = sb[e] != 0u;
-        col_d1<DV>(xy, rq, r, sb, d);
-        float post = __uint_as_float(jl.y);
-#pragma unroll
-        for (int e = 0; e < DV; ++e) post = post + d[e];
-        if (first_set<DV>(r, fl) == i && post <= 0.f) set_column<DV>(W, jl, r, m);
-      });
-      wave_sync();
-    }
+    if (ok) iteration1<DV>(a, W, xy, smap, ncand, lane);
     const bool conv = ok && W.nset <= kScreenMaxSet &&
                       __ballot(lane < a.words_m && W.rbits[lane] != 0u) == 0ull;
     if (conv) {
