@@ -1228,10 +1228,25 @@ template <int CPT, int PW>
 __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   const Lds L{lds_raw};
+  const int tid = threadIdx.x;
+  if (!a.stream) {
+    // Batched: nothing to do once every shot is done (the screen may have
+    // finished them all); a launch beside the screen ends at once unless the
+    // whole screen launch has begun (it must not keep the screen off the
+    // device, since it may wait for the screen's list).
+    if (tid == 0) {
+      bool quit = __hip_atomic_load(&a.st->done, __ATOMIC_RELAXED, AGENT) >= (unsigned long long)a.shots;
+      if (a.helper &&
+          __hip_atomic_load(&a.st->screen_begun, __ATOMIC_RELAXED, AGENT) < (uint32_t)a.screen_grid)
+        quit = true;
+      L.misc()[30] = quit ? 1 : 0;
+    }
+    __syncthreads();
+    if (L.misc()[30]) return;
+  }
   Res<CPT, PW> R;
   load_res<CPT, PW>(a.g, L, R);
   unsigned long long nruns = 0, niters = 0;
-  const int tid = threadIdx.x;
   if (a.stream) {
     // Serving.  A launch that the host has replaced (it waited behind another
     // persistent kernel on a shared hardware queue) ends before touching
@@ -1256,8 +1271,20 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
   if (a.shot_list && tid == 0) nclaim = __hip_atomic_load(&a.st->listed, __ATOMIC_RELAXED, AGENT);
   // Shots per claim: 8, fewer when there are under 32 per workgroup (a short
   // list from the screen), so that every workgroup gets some.
-  const long long chunk = nclaim >= 32ll * gridDim.x ? 8 : nclaim >= 4ll * gridDim.x ? 2 : 1;
+  // (one at a time beside the screen, whose list is still growing)
+  const long long chunk =
+      a.helper ? 1 : nclaim >= 32ll * gridDim.x ? 8 : nclaim >= 4ll * gridDim.x ? 2 : 1;
   auto shot_at = [&](long long q) -> long long { return a.shot_list ? (long long)a.shot_list[q] : q; };
+  // Beside the screen: an entry below the listed count is written at once by
+  // the running screen wave that counted it; it is read with acquire order,
+  // so that what the screen wrote before it (the shot's latency) is seen.
+  auto listed_at = [&](long long q) -> long long {
+    for (;;) {
+      const int32_t v = __hip_atomic_load(&a.shot_list[q], __ATOMIC_ACQUIRE, AGENT);
+      if (v >= 0) return (long long)v;
+      __builtin_amdgcn_s_sleep(2);
+    }
+  };
   bool exhausted = false;         // thread 0 only
   int work_hint = -1;             // thread 0 only: queue length read late in the last step, -1 unknown
   bool idling = false;            // thread 0 only, serving: in an idle stretch since idle_since
@@ -1303,7 +1330,26 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
           uint32_t cx;
           if (ring_pop(&a.st->ctxq, a.ctx_ring, &cx)) spare = (int)cx;
         }
-        if (spare >= 0) {
+        if (spare >= 0 && a.helper) {
+          // A claimed position past the listed count is kept until the
+          // screen lists a shot there, or ends without doing so.
+          if (cnext >= cend) {
+            cnext = (long long)__hip_atomic_fetch_add(&a.st->next_shot, 1ull, __ATOMIC_RELAXED, AGENT);
+            cend = cnext + 1;
+          }
+          if (cnext >= nclaim) {
+            nclaim = __hip_atomic_load(&a.st->listed, __ATOMIC_RELAXED, AGENT);
+            if (cnext >= nclaim && __hip_atomic_load(&a.st->screen_live, __ATOMIC_RELAXED, AGENT) <= 0) {
+              nclaim = __hip_atomic_load(&a.st->listed, __ATOMIC_RELAXED, AGENT);  // final
+              if (cnext >= nclaim) exhausted = true;
+            }
+          }
+          if (cnext < nclaim) {
+            kind = 2;
+            shot = listed_at(cnext++);
+            item = (uint32_t)spare;
+          }
+        } else if (spare >= 0) {
           if (cnext >= cend) {
             const unsigned long long b = __hip_atomic_fetch_add(
                 &a.st->next_shot, (unsigned long long)chunk, __ATOMIC_RELAXED, AGENT);
@@ -1375,7 +1421,7 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       box[1] = (int)item;
       box[2] = (int)(shot & 0xFFFFFFFF);
       box[3] = (int)(shot >> 32);
-      const long long nx = (kind == 2 && cnext < cend) ? shot_at(cnext) : -1;
+      const long long nx = (kind == 2 && cnext < cend && !a.helper) ? shot_at(cnext) : -1;
       box[4] = (int)(nx & 0xFFFFFFFF);
       box[5] = (int)(nx >> 32);
     }

@@ -82,6 +82,8 @@ struct Lane {
   bool pending = false;            // `done` has been recorded
   int64_t last_shots = 0;          // shots of the last call (checked by bsd_code_sync)
   hipStream_t cap_stream = nullptr;
+  hipStream_t side = nullptr;      // the dense decoder launched beside the screen
+  hipEvent_t ev_side = nullptr;    // end of that launch
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<char> gkey;
@@ -178,6 +180,8 @@ void lane_free(Lane* l) {
   lane_wait(l);
   drop_graph(l);
   if (l->cap_stream) hipStreamDestroy(l->cap_stream);
+  if (l->side) hipStreamDestroy(l->side);
+  if (l->ev_side) hipEventDestroy(l->ev_side);
   ws_free(l->ws);
   hipFree(l->d_list);
   for (hipEvent_t e : {l->ev0, l->ev1, l->evs, l->done})
@@ -805,6 +809,10 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
   const ScreenArgs sa = screen_args(c, p, a, ft);
   const int sgrid = screen_grid(c, shots, 1);
   const int sgrid2 = screen_grid(c, shots, 2);
+  if (screen) {  // (the screen's progress, for the dense decoder beside it)
+    a.screen_grid = sa.t2 ? sgrid2 : sgrid;
+    a.screen_waves = a.screen_grid * ((sa.t2 ? kScreen2Block : kScreenBlock) / 64);
+  }
   if (p->flags & BSD_FLAG_GRAPH) {
     // Replay the recorded reset + decode kernels when the arguments repeat.
     std::vector<char> key(sizeof a + 3 * sizeof(int));
@@ -835,8 +843,25 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     HIP_OR_FAIL(launch_batch_reset(a, s));
     HIP_OR_FAIL(hipEventRecord(l->ev0, s));
     if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, sgrid2, s));
+    if (screen) {
+      // A dense decoder beside the screen, on a second stream: its
+      // workgroups start as the screen's leave the device and take the
+      // listed shots while the screen still runs.  The launch after the
+      // screen takes whatever it leaves (and ends at once when it left
+      // nothing).
+      if (!l->side) {
+        HIP_OR_FAIL(hipStreamCreateWithFlags(&l->side, hipStreamNonBlocking));
+        HIP_OR_FAIL(hipEventCreateWithFlags(&l->ev_side, hipEventDisableTiming));
+      }
+      BatchArgs h = a;
+      h.helper = 1;
+      HIP_OR_FAIL(hipStreamWaitEvent(l->side, l->ev0, 0));
+      HIP_OR_FAIL(launch_batched(h, c->grid, c->block, c->cpt, c->pw, c->lds, l->side));
+      HIP_OR_FAIL(hipEventRecord(l->ev_side, l->side));
+    }
     HIP_OR_FAIL(hipEventRecord(l->evs, s));
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
+    if (screen) HIP_OR_FAIL(hipStreamWaitEvent(s, l->ev_side, 0));
     HIP_OR_FAIL(hipEventRecord(l->ev1, s));
   }
   HIP_OR_FAIL(hipEventRecord(l->done, s));

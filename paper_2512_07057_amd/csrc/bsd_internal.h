@@ -101,6 +101,8 @@ struct BatchState {
   uint32_t stop;           // nonzero: end the kernel
   uint32_t poll_token;     // 1 while a workgroup is reading the host counters
   int32_t listed;          // shots the screen handed to the dense decoder
+  uint32_t screen_begun;   // workgroups of the screen launch that have begun
+  int32_t screen_live;     // waves of the screen launch that have not finished
   unsigned long long done2;  // shots the screen finished at iteration 2
   uint32_t sticky;         // errors of earlier calls on this workspace, until reported
 };
@@ -168,6 +170,15 @@ struct BatchArgs {
   // screen has already written the outputs of the others and counted them
   // as done, and its share of each listed shot's latency.
   const int32_t* shot_list;
+  // A launch beside the screen (helper = 1) starts on the workgroups the
+  // screen leaves and takes listed shots while the screen still lists them
+  // (entries -1 until written); it ends at once unless every one of the
+  // screen's screen_grid workgroups had begun, so that it never holds the
+  // device from a screen that has not started.  The launch after the screen
+  // finishes whatever is left.
+  int32_t helper;
+  int32_t screen_grid;
+  int32_t screen_waves;   // reset: the screen launch's waves (0: no screen)
   uint32_t* work_ring;
   uint32_t work_cap;      // power of two
   uint32_t* ctx_ring;
@@ -219,7 +230,7 @@ struct ScreenArgs {
   uint8_t* conv;
   uint32_t* lat;               // or NULL
   BatchState* st;              // error, done, done2, runs, iterations, listed
-  int32_t* list;               // [shots] shots for the dense decoder
+  int32_t* list;               // [shots] shots for the dense decoder (-1 until written)
 };
 constexpr int kScreenBlock = 512;        // iteration 1: eight shots in flight per workgroup
 constexpr int kScreen1MinWaves = 4;      // iteration 1: waves per SIMD the registers must allow

@@ -10,6 +10,10 @@ __global__ void k_batch_reset(BatchArgs a) {
   const int n = gridDim.x * blockDim.x;
   for (uint32_t q = i; q < a.work_cap; q += n) a.work_ring[q] = 0u;
   for (uint32_t q = i; q < a.ctx_cap; q += n) a.ctx_ring[q] = q < (uint32_t)a.nctx ? q + 1u : 0u;
+  if (a.shot_list) {  // the screen's list for the dense decoder: entries -1 until written
+    int32_t* list = const_cast<int32_t*>(a.shot_list);
+    for (long long q = i; q < a.shots; q += n) list[q] = -1;
+  }
   if (i == 0) {
     a.st->next_shot = 0;
     a.st->done = 0;
@@ -32,6 +36,8 @@ __global__ void k_batch_reset(BatchArgs a) {
     a.st->poll_token = 0;
     a.st->listed = 0;
     a.st->done2 = 0;
+    a.st->screen_begun = 0;
+    a.st->screen_live = a.screen_waves;
   }
 }
 

@@ -799,10 +799,14 @@ __device__ __forceinline__ void write_shot(const ScreenArgs& a, const WaveLds1& 
   if (lane == 0) a.conv[shot] = 1;
 }
 
+// Appends a shot to the dense decoder's list.  The entry is stored with
+// release order: a decoder launched beside the screen may take it at once,
+// and must see what was written before (the shot's latency so far).
 __device__ __forceinline__ void list_dense(const ScreenArgs& a, long long shot) {
   const int q = __hip_atomic_fetch_add(&a.st->listed, 1, __ATOMIC_RELAXED, AGENT);
-  a.list[q] = (int32_t)shot;
+  __hip_atomic_store(&a.list[q], (int32_t)shot, __ATOMIC_RELEASE, AGENT);
 }
+
 
 // Flipped rows and their pairs; false when the lists overflow.
 __device__ __forceinline__ bool flipped_pairs(const ScreenArgs& a, WaveLds1& W, const int32_t* rptr,
@@ -834,6 +838,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
                   wv * map_bytes(m);
   if (lane == 0) smap[m] = 0;  // absent row slots
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.st->screen_begun, 1u, __ATOMIC_RELAXED, AGENT);
   const long long nwaves = (long long)gridDim.x * kWaves1;
   uint32_t done = 0, err = 0;
   long long shot = (long long)blockIdx.x * kWaves1 + wv;
@@ -857,10 +862,11 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
     if (conv) {
       write_shot<V>(a, W, shot, lane);
       ++done;
+      if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     } else if (lane == 0) {
+      if (a.lat) a.lat[shot] = (uint32_t)wall_clock64() - t0;
       list_dense(a, shot);
     }
-    if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     wave_sync();  // the next shot reuses this wave's LDS
   }
   if (lane == 0 && done) {
@@ -869,6 +875,7 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
     __hip_atomic_fetch_add(&a.st->iterations, (unsigned long long)done, __ATOMIC_RELAXED, AGENT);
   }
   if (__ballot(err != 0u) && lane == 0) atomicOr(&a.st->error, 1u);
+  if (lane == 0) __hip_atomic_fetch_add(&a.st->screen_live, -1, __ATOMIC_RELAXED, AGENT);
 }
 
 // Iterations 1 and 2 in one kernel.  Each wave first takes its share of
@@ -901,6 +908,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
   uint8_t* imap = smap + map_bytes(m);
   if (lane == 0) smap[m] = 0;  // absent row slots
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.st->screen_begun, 1u, __ATOMIC_RELAXED, AGENT);
   const long long nwaves = (long long)gridDim.x * kWaves2;
   uint32_t done = 0, done2 = 0, err = 0;
   long long shot = (long long)blockIdx.x * kWaves2 + wv;
@@ -923,14 +931,15 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     if (conv) {
       write_shot<V>(a, W, shot, lane);
       ++done;
+      if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     } else if (lane == 0) {
+      if (a.lat) a.lat[shot] = (uint32_t)wall_clock64() - t0;
       const int q = ok ? atomicAdd(&gl->count, 1) : kWgList;
       if (q < kWgList)
         __hip_atomic_store(&gl->shot[q], (int32_t)shot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       else
         list_dense(a, shot);
     }
-    if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
     wave_sync();  // the next shot reuses this wave's LDS
   }
   if (lane == 0) atomicAdd(&gl->finished, 1);
@@ -967,10 +976,11 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     if (ok) {
       write_shot<V>(a, W, s2, lane);
       ++done2;
+      if (a.lat && lane == 0) a.lat[s2] += (uint32_t)wall_clock64() - t0;
     } else if (lane == 0) {
+      if (a.lat) a.lat[s2] += (uint32_t)wall_clock64() - t0;
       list_dense(a, s2);
     }
-    if (a.lat && lane == 0) a.lat[s2] += (uint32_t)wall_clock64() - t0;
     wave_sync();
   }
   if (lane == 0 && (done | done2)) {
@@ -981,6 +991,7 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
     if (done2) __hip_atomic_fetch_add(&a.st->done2, (unsigned long long)done2, __ATOMIC_RELAXED, AGENT);
   }
   if (__ballot(err != 0u) && lane == 0) atomicOr(&a.st->error, 1u);
+  if (lane == 0) __hip_atomic_fetch_add(&a.st->screen_live, -1, __ATOMIC_RELAXED, AGENT);
 }
 
 size_t lds1(int m) { return table_bytes(m, 1) + align16(kWaves1 * sizeof(WaveLds1)) + kWaves1 * map_bytes(m); }
