@@ -354,8 +354,12 @@ def main():
                     "screened_shots": int(stats[-1]["screened_shots"]),
                     "screened_at_t2": int(stats[-1]["screened2_shots"]),
                     "dense_shots": int(shots - stats[-1]["screened_shots"]),
-                    "what": "screen: k_screen12 (iterations 1 and 2 of the initial run, one "
-                            "wave per shot); dense: k_batched (persistent decoder for the rest)"},
+                    "what": "screen_ms: from the call's start to the end of k_screen12 "
+                            "(iterations 1 and 2 of the initial run, one wave per shot); "
+                            "dense_ms: the rest of the call, k_batched (the persistent decoder "
+                            "for the listed shots) launched beside the screen finishing the "
+                            "shots listed last, then the k_batched launch after the screen, "
+                            "which ends at once when nothing is left"},
         "work_rate": {"edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
                       "bp_iterations_per_step": iters,
                       "what": "BP iterations x Tanner edges per second of kernel time; a work "

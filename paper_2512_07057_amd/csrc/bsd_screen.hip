@@ -382,7 +382,7 @@ __device__ __forceinline__ void set_column(WaveLds1& W, const uint4& jl, const i
 // alpha is at most 1 a first pass reads only the columns' rows: a column
 // with one flipped row whose record says that one detector cannot decide it
 // has a positive posterior, and the others are queued and summed in full,
-// one per lane.  More than kMaxHeavy queued columns: the full pass instead.
+// one per lane (once kMaxHeavy are queued, the others as they are found).
 template <int DV>
 __device__ __forceinline__ void iteration1(const ScreenArgs& a, WaveLds1& W, const float2* xy,
                                            const uint8_t* smap, int ncand, int lane) {
@@ -413,24 +413,24 @@ __device__ __forceinline__ void iteration1(const ScreenArgs& a, WaveLds1& W, con
       if (first_set<DV>(r, fl) != i) return;
       if (nf < 2 && !((rq.x >> 14) & 1u)) return;
       const int q = atomicAdd(&W.nheavy, 1);
-      if (q < kMaxHeavy) W.hpos[q] = pos;
+      if (q < kMaxHeavy)
+        W.hpos[q] = pos;
+      else
+        decide(rq, a.edge_col[pos], r, sb);  // (the queue is full)
     });
     wave_sync();
-    const int nq = W.nheavy;
-    if (nq <= kMaxHeavy) {
-      if (lane < nq) {
-        const int pos = W.hpos[lane];
-        const uint4 rq = a.edge_rows[pos];
-        const uint4 jl = a.edge_col[pos];
-        int r[DV];
-        uint32_t sb[DV];
-        col_rows<DV>(rq, m, r);
-        col_map<DV>(smap, r, sb);
-        decide(rq, jl, r, sb);
-      }
-      wave_sync();
-      return;
+    if (lane < min(W.nheavy, kMaxHeavy)) {
+      const int pos = W.hpos[lane];
+      const uint4 rq = a.edge_rows[pos];
+      const uint4 jl = a.edge_col[pos];
+      int r[DV];
+      uint32_t sb[DV];
+      col_rows<DV>(rq, m, r);
+      col_map<DV>(smap, r, sb);
+      decide(rq, jl, r, sb);
     }
+    wave_sync();
+    return;
   }
   for_pairs<kUnroll>(a, W, W.rows, ncand, lane, [&](int, int i, int, const uint4& rq, const uint4& jl) {
     int r[DV];
@@ -616,9 +616,8 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
   // Posteriors (eq. (3)) of the columns next to S2, each taken by its lowest
   // S2 row: first with every S2 message taken negative; the columns this
   // leaves open are queued and then taken one per lane with the S2 messages
-  // exact (so that the pass over all pairs stays short and uniform; with
-  // more than kMaxHeavy of them the pass runs again and takes them as it
-  // finds them).  A
+  // exact (so that the pass over all pairs stays short and uniform; once
+  // kMaxHeavy are queued the pass takes the others as it finds them).  A
   // column whose bounded posterior is still not positive and that used a
   // bound for a row outside S2 is listed, and those rows are marked for a
   // scan.
@@ -630,24 +629,6 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
     W.nheavy = 0;
     W.flw[0] = W.flw[1] = 0u;
   }
-  wave_sync();
-  for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint4& jl) {
-    int r[DV], q[DV];
-    bool in2[DV];
-    float mag[DV];
-    col_rows<DV>(rq, m, r);
-    d2_rows<DV>(imap, r, false, q);
-#pragma unroll
-    for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
-    if (first_set<DV>(r, in2) != i) return;
-    d2_mags<DV>(W, e1min, r, q, (int)jl.x, alpha, gdmin, mag);
-    float lb = __uint_as_float(jl.y);
-#pragma unroll
-    for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
-    if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
-    const int qh = atomicAdd(&W.nheavy, 1);
-    if (qh < kMaxHeavy) W.hpos[qh] = pos;
-  });
   wave_sync();
   // A column left open by the bound: the S2 messages exact (the sign of each
   // from its row's parity and the sign of E(1) on the edge).
@@ -679,34 +660,36 @@ __device__ bool iteration2(const ScreenArgs& a, WaveLds2& W, const float2* xy, c
     for (int e = 0; e < DV; ++e)
       if (r[e] < m && q[e] < 0) set_bit(W.xbits, r[e]);
   };
-  if (W.nheavy <= kMaxHeavy) {
-    if (lane < W.nheavy) {
-      const int pos = W.hpos[lane];
-      const uint4 rq = a.edge_rows[pos];
-      const uint4 jl = a.edge_col[pos];
-      int r[DV], q[DV];
-      float mag[DV];
-      col_rows<DV>(rq, m, r);
-      d2_slots<DV>(W, imap, e1min, r, (int)jl.x, alpha, gdmin, false, q, mag);
-      open_column(pos, rq, jl, r, q, mag);
-    }
-  } else {
-    // (too many to queue: the pass again, open columns taken at once)
-    for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint4& jl) {
-      int r[DV], q[DV];
-      bool in2[DV];
-      float mag[DV];
-      col_rows<DV>(rq, m, r);
-      d2_rows<DV>(imap, r, false, q);
+  for_pairs<kUnroll2>(a, W, W.rows, np, lane, [&](int, int i, int pos, const uint4& rq, const uint4& jl) {
+    int r[DV], q[DV];
+    bool in2[DV];
+    float mag[DV];
+    col_rows<DV>(rq, m, r);
+    d2_rows<DV>(imap, r, false, q);
 #pragma unroll
-      for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
-      if (first_set<DV>(r, in2) != i) return;
-      d2_mags<DV>(W, e1min, r, q, (int)jl.x, alpha, gdmin, mag);
-      float lb = __uint_as_float(jl.y);
+    for (int e = 0; e < DV; ++e) in2[e] = q[e] >= 0;
+    if (first_set<DV>(r, in2) != i) return;
+    d2_mags<DV>(W, e1min, r, q, (int)jl.x, alpha, gdmin, mag);
+    float lb = __uint_as_float(jl.y);
 #pragma unroll
-      for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
-      if (lb <= 0.f) open_column(pos, rq, jl, r, q, mag);
-    });
+    for (int e = 0; e < DV; ++e) lb = lb + (in2[e] ? -mag[e] : mag[e]);
+    if (lb > 0.f) return;  // e-hat_j = 0 (eq. (4))
+    const int qh = atomicAdd(&W.nheavy, 1);
+    if (qh < kMaxHeavy)
+      W.hpos[qh] = pos;
+    else
+      open_column(pos, rq, jl, r, q, mag);  // (the queue is full)
+  });
+  wave_sync();
+  if (lane < min(W.nheavy, kMaxHeavy)) {
+    const int pos = W.hpos[lane];
+    const uint4 rq = a.edge_rows[pos];
+    const uint4 jl = a.edge_col[pos];
+    int r[DV], q[DV];
+    float mag[DV];
+    col_rows<DV>(rq, m, r);
+    d2_slots<DV>(W, imap, e1min, r, (int)jl.x, alpha, gdmin, false, q, mag);
+    open_column(pos, rq, jl, r, q, mag);
   }
   wave_sync();
   const int nexact = W.nexact;
