@@ -91,6 +91,54 @@ def test_screen_equals_dense_first_iteration(bsd, wl, hot, shots):
         assert st["screened2_shots"] > 0.8 * (shots - st1["screened_shots"])
 
 
+@pytest.mark.parametrize("alpha", [1.0, 1.3])
+def test_screen_alpha_beyond_the_single_detector_flag(bsd, alpha):
+    """Iteration 1's first pass trusts a per-column flag proved for alpha <= 1:
+    at alpha = 1 (the bound's edge) it is used, above 1 the full pass runs.
+    Both equal the call without the screen, on W2 at 4x and 20x the priors
+    (many flipped rows, full queues) and on W1."""
+    screened = 0
+    for wl, hot, shots in (("W2", 4, 4000), ("W2", 20, 1000), ("W1", 0, 5000)):
+        W = workloads.WORKLOADS[wl]
+        code = _code(bsd, W.problem_key)
+        if hot:
+            syn = gc.samples(wl, shots, seed=23, hot=hot)["syndromes"]
+        else:
+            syn = workloads.shots_for(W, shots=shots)["syndromes"]
+        syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
+        P = W.params
+        outs = {}
+        for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN)):
+            prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
+                                  P.num_results, alpha, bsd.MODE_BATCHED, flags)
+            r = code.decode(syn, prm)
+            torch.cuda.synchronize()
+            outs[name] = (_np(r), r["stats"])
+            gc.log("  alpha", alpha, wl, name, r["stats"])
+        _check_same(outs["screen"][0], outs["no_screen"][0], f"{wl} alpha {alpha}")
+        screened += outs["screen"][1]["screened_shots"]
+    assert screened > 0
+
+
+def test_screen_tiny_batches(bsd):
+    """Batches smaller than a workgroup's waves or than the dense decoder's
+    grid, some shots handed on (W2 at 40x the priors): the screen, the
+    decoder launched beside it and the one after it end cleanly and agree
+    with the call without the screen."""
+    W = workloads.WORKLOADS["W2"]
+    code = _code(bsd, W.problem_key)
+    for shots in (1, 7, 63, 300):
+        syn = gc.samples("W2", shots, seed=31 + shots, hot=40 if shots < 300 else 0)["syndromes"]
+        syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
+        outs = {}
+        for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN)):
+            r = code.decode(syn, _params(bsd, W.params, flags))
+            torch.cuda.synchronize()
+            outs[name] = _np(r)
+        gc.log("  tiny", shots)
+        _check_same(outs["screen"], outs["no_screen"], f"{shots} shots")
+
+
 def test_screen_iteration2_with_schedule(bsd):
     """Iteration 2 scaled by the schedule's second entry (iteration 1 by the
     first): equal to the call without the screen."""
