@@ -1276,11 +1276,15 @@ __global__ void __launch_bounds__(max_block_for(CPT)) k_batched(BatchArgs a) {
       a.helper ? 1 : nclaim >= 32ll * gridDim.x ? 8 : nclaim >= 4ll * gridDim.x ? 2 : 1;
   auto shot_at = [&](long long q) -> long long { return a.shot_list ? (long long)a.shot_list[q] : q; };
   // Beside the screen: an entry below the listed count is written at once by
-  // the running screen wave that counted it; it is read with acquire order,
-  // so that what the screen wrote before it (the shot's latency) is seen.
+  // the running screen wave that counted it.  When latencies are measured it
+  // is read with acquire order, so that what the screen wrote before it (the
+  // shot's latency so far) is seen; the shot itself needs nothing else the
+  // screen wrote, and an acquire (an invalidation of this XCD's L2, which
+  // the screen's waves there rely on) is not paid otherwise.
   auto listed_at = [&](long long q) -> long long {
     for (;;) {
-      const int32_t v = __hip_atomic_load(&a.shot_list[q], __ATOMIC_ACQUIRE, AGENT);
+      const int32_t v = a.lat ? __hip_atomic_load(&a.shot_list[q], __ATOMIC_ACQUIRE, AGENT)
+                              : __hip_atomic_load(&a.shot_list[q], __ATOMIC_RELAXED, AGENT);
       if (v >= 0) return (long long)v;
       __builtin_amdgcn_s_sleep(2);
     }

@@ -71,6 +71,10 @@ uint32_t pow2_at_least(uint64_t x) {
 // slots), the screen's shot list, events, and the HIP graph of the last call
 // (BSD_FLAG_GRAPH).  Calls on one stream run in stream order, so they share
 // it; calls on different streams have their own and may run concurrently.
+// The decoder beside the screen runs while the screen hands on less than this
+// share of a call's shots.
+constexpr double kBesideMaxListed = 0.02;
+
 struct Lane {
   hipStream_t stream = nullptr;
   std::mutex mu;                   // held while a call enqueues its work
@@ -84,6 +88,8 @@ struct Lane {
   hipStream_t cap_stream = nullptr;
   hipStream_t side = nullptr;      // the dense decoder launched beside the screen
   hipEvent_t ev_side = nullptr;    // end of that launch
+  double listed_frac = 0.0;        // share of shots the screen handed on in the last
+                                   //   synchronous call (decides the launch beside it)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<char> gkey;
@@ -843,12 +849,15 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     HIP_OR_FAIL(launch_batch_reset(a, s));
     HIP_OR_FAIL(hipEventRecord(l->ev0, s));
     if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, sgrid2, s));
-    if (screen) {
-      // A dense decoder beside the screen, on a second stream: its
-      // workgroups start as the screen's leave the device and take the
-      // listed shots while the screen still runs.  The launch after the
-      // screen takes whatever it leaves (and ends at once when it left
-      // nothing).
+    // A dense decoder beside the screen, on a second stream: its workgroups
+    // start as the screen's leave the device and take the listed shots while
+    // the screen still runs.  The launch after the screen takes whatever it
+    // leaves (and ends at once when it left nothing).  It pays only when the
+    // screen hands on few shots (the dense work then hides under the
+    // screen's last waves); with more, running beside the screen slows both,
+    // so the share of the lane's last synchronous call decides.
+    const bool beside = screen && l->listed_frac < kBesideMaxListed;
+    if (beside) {
       if (!l->side) {
         HIP_OR_FAIL(hipStreamCreateWithFlags(&l->side, hipStreamNonBlocking));
         HIP_OR_FAIL(hipEventCreateWithFlags(&l->ev_side, hipEventDisableTiming));
@@ -861,7 +870,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     }
     HIP_OR_FAIL(hipEventRecord(l->evs, s));
     HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
-    if (screen) HIP_OR_FAIL(hipStreamWaitEvent(s, l->ev_side, 0));
+    if (beside) HIP_OR_FAIL(hipStreamWaitEvent(s, l->ev_side, 0));
     HIP_OR_FAIL(hipEventRecord(l->ev1, s));
   }
   HIP_OR_FAIL(hipEventRecord(l->done, s));
@@ -880,6 +889,7 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
   }
   if (h.done != (unsigned long long)shots)
     return fail(BSD_EDEVICE, "batched decoder finished %llu of %lld shots", h.done, (long long)shots);
+  if (screen) l->listed_frac = (double)h.listed / (double)shots;
   if (stats) {
     float ms = 0.f, sms = 0.f;
     (void)hipEventElapsedTime(&ms, l->ev0, l->ev1);

@@ -782,12 +782,17 @@ __device__ __forceinline__ void write_shot(const ScreenArgs& a, const WaveLds1& 
   if (lane == 0) a.conv[shot] = 1;
 }
 
-// Appends a shot to the dense decoder's list.  The entry is stored with
-// release order: a decoder launched beside the screen may take it at once,
-// and must see what was written before (the shot's latency so far).
+// Appends a shot to the dense decoder's list (an atomic store: a decoder
+// launched beside the screen may take it at once).  When latencies are
+// measured the store has release order, so that the decoder sees the shot's
+// latency so far; otherwise nothing written before it is needed there, and a
+// release (a write-back of this XCD's L2) is not paid.
 __device__ __forceinline__ void list_dense(const ScreenArgs& a, long long shot) {
   const int q = __hip_atomic_fetch_add(&a.st->listed, 1, __ATOMIC_RELAXED, AGENT);
-  __hip_atomic_store(&a.list[q], (int32_t)shot, __ATOMIC_RELEASE, AGENT);
+  if (a.lat)
+    __hip_atomic_store(&a.list[q], (int32_t)shot, __ATOMIC_RELEASE, AGENT);
+  else
+    __hip_atomic_store(&a.list[q], (int32_t)shot, __ATOMIC_RELAXED, AGENT);
 }
 
 
