@@ -782,6 +782,24 @@ __device__ __forceinline__ void write_shot(const ScreenArgs& a, const WaveLds1& 
   if (lane == 0) a.conv[shot] = 1;
 }
 
+// Outputs of a shot whose syndrome is all zero: from E(0) = Lambda > 0 every
+// message at t = 1 is positive, e-hat(1) = 0 satisfies s = 0, and the run
+// stops there (the same outputs as the full iteration-1 path).
+template <int V>
+__device__ __forceinline__ void write_zero_shot(const ScreenArgs& a, long long shot, int lane) {
+  write_corrections<V>(a, a.corr + shot * a.n, -1, lane);
+  if (lane < a.k) a.flips[shot * a.k + lane] = 0;
+  if (lane == 0) a.conv[shot] = 1;
+}
+
+// True in every lane when the syndrome held in `v` (8-byte rows) is all zero.
+__device__ __forceinline__ bool syndrome_zero(const uint2 (&v)[kSynRegs]) {
+  uint32_t any = 0u;
+#pragma unroll
+  for (int u = 0; u < kSynRegs; ++u) any |= v[u].x | v[u].y;
+  return __ballot(any != 0u) == 0ull;
+}
+
 // Appends a shot to the dense decoder's list (an atomic store: a decoder
 // launched beside the screen may take it at once).  When latencies are
 // measured the store has release order, so that the decoder sees the shot's
@@ -834,6 +852,13 @@ __global__ void __launch_bounds__(kScreenBlock, kScreen1MinWaves) k_screen1(Scre
   if (a.syn8 && shot < a.shots) load_syn_regs(a, shot, lane, sv);
   for (; shot < a.shots; shot += nwaves) {
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
+    if (a.syn8 && syndrome_zero(sv)) {  // (load_syn_regs zeroes the rows past m)
+      if (shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
+      write_zero_shot<V>(a, shot, lane);
+      ++done;
+      if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
+      continue;
+    }
     err |= syndrome_in(a, shot, sv, W, smap, lane);
     if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
     W.rbits[lane] = W.sbits[lane];
@@ -904,6 +929,13 @@ __global__ void __launch_bounds__(kScreen2Block, kScreen2MinWaves) k_screen12(Sc
   if (a.syn8 && shot < a.shots) load_syn_regs(a, shot, lane, sv);
   for (; shot < a.shots; shot += nwaves) {
     const uint32_t t0 = a.lat ? (uint32_t)wall_clock64() : 0u;
+    if (a.syn8 && syndrome_zero(sv)) {  // (load_syn_regs zeroes the rows past m)
+      if (shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
+      write_zero_shot<V>(a, shot, lane);
+      ++done;
+      if (a.lat && lane == 0) a.lat[shot] = (uint32_t)wall_clock64() - t0;
+      continue;
+    }
     err |= syndrome_in(a, shot, sv, W, smap, lane);
     if (a.syn8 && shot + nwaves < a.shots) load_syn_regs(a, shot + nwaves, lane, sv);
     W.rbits[lane] = W.sbits[lane];
