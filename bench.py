@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shots", type=int, default=100_000)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="streams the timed calls are spread over (each a workspace of its own)")
     ap.add_argument("--plain-shots", type=int, default=10_000)
     ap.add_argument("--legs", default=",".join(LEGS),
                     help="comma-separated extra legs to run after the headline: " + ",".join(LEGS))
@@ -296,23 +298,61 @@ def main():
     }
     prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
                           P.num_results, P.alpha, bsd.MODE_BATCHED)
-    for _ in range(args.warmup):
-        code.decode(syn, prm, out=out)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(code.decode(syn, prm, out=out)["stats"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
+    # Calls enqueued back to back (asynchronous, as a pipeline of batches
+    # makes them) on `nstreams` streams in turn, each stream with its own
+    # workspace in the library and its own output buffers; one error check
+    # per stream at the end.  HIP events on the timing stream, which waits
+    # for every call, give the device time.
+    # The streams are made once; the synchronous calls below run on the
+    # first (a stream's workspace, its helper stream included, is reused).
+    pool = [torch.cuda.Stream() for _ in range(max(args.streams, 1))]
+    extra_outs = [{k: torch.empty_like(v) for k, v in out.items()}
+                  for _ in range(len(pool) - 1)]
+
+    def timed_async(nstreams):
+        streams = pool[:nstreams]
+        outs = ([out] + extra_outs)[:nstreams]
+        for st, o in zip(streams, outs):
+            for _ in range(max(args.warmup, 1)):
+                code.decode(syn, prm, out=o, stream=st)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for st in streams:
+            st.wait_stream(torch.cuda.current_stream())
+        for i in range(args.steps):
+            code.decode(syn, prm, out=outs[i % nstreams], stream=streams[i % nstreams],
+                        sync=False)
+        for st in streams:
+            torch.cuda.current_stream().wait_stream(st)
+        e1.record()
+        for st in streams:
+            code.sync(st)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        same = all(bool((o["corrections"] == out["corrections"]).all().item()) for o in outs[1:])
+        return wall_ms, e0.elapsed_time(e1) / args.steps, same
+
+    ms_per_step, dev_ms, same_out = timed_async(args.streams)
+    assert same_out, "outputs differ between streams"
     value = shots / (ms_per_step / 1e3)
+    one_stream = timed_async(1) if args.streams != 1 else None
+    # The same number of synchronous calls, each reporting its kernel times
+    # and counts (and waiting for its results before the next is enqueued).
+    stats = []
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(code.decode(syn, prm, out=out, stream=pool[0])["stats"])
+    torch.cuda.synchronize()
+    sync_ms = (time.perf_counter() - ts) / args.steps * 1e3
     kms = float(np.mean([s["kernel_ms"] for s in stats]))
     sms = float(np.mean([s["screen_ms"] for s in stats]))
     iters = float(np.mean([s["iterations"] for s in stats]))
 
     # Per-shot device latency and the logical error rate, from one more call.
-    r = code.decode(syn, prm, out=out, latency=True)
+    r = code.decode(syn, prm, out=out, latency=True, stream=pool[0])
     torch.cuda.synchronize()
     lat_us = r["latency_ticks"].cpu().numpy().astype(np.float64) / 100.0  # 100 MHz clock
     conv = out["converged"].cpu().numpy().astype(bool)
@@ -320,11 +360,13 @@ def main():
 
     # Roofline: the HBM floor of the call's mandatory traffic, syndromes in
     # (m bytes per shot) and corrections, logical flips and the converged
-    # flag out (n + k + 1 bytes per shot), over the decoding kernels' event
-    # time.  The messages of every BP run live in LDS and never reach HBM.
+    # flag out (n + k + 1 bytes per shot), over the device time per call in
+    # the timed region (HIP events on the calls' stream, the gaps between
+    # calls included).  The messages of every BP run live in LDS and never
+    # reach HBM.
     io_bytes_per_shot = pr.m + pr.n + pr.k + 1
     io_bytes = float(io_bytes_per_shot * shots)
-    achieved = io_bytes / (kms * 1e-3) / 1e9
+    achieved = io_bytes / (dev_ms * 1e-3) / 1e9
     tr = measured_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
@@ -349,17 +391,24 @@ def main():
                                "(iteration 1, and iteration 2 if it needs it) plus, for a shot "
                                "the screen hands on, the persistent decoder's time from its "
                                "initial BP run to its result write"},
+        "device_ms_per_step": dev_ms,
+        "streams": args.streams,
+        "one_stream": ({"ms_per_step": one_stream[0], "device_ms_per_step": one_stream[1],
+                        "shots_per_s": shots / (one_stream[0] * 1e-3)} if one_stream else None),
+        "sync_calls": {"ms_per_call": sync_ms, "shots_per_s": shots / (sync_ms * 1e-3),
+                       "kernel_ms": kms,
+                       "what": "the same calls made synchronously (each returns its stats "
+                               "after its results are written); kernel_ms is the call's HIP-event "
+                               "time on its stream"},
         "kernel_ms": kms,
         "kernels": {"screen_ms": sms, "dense_ms": kms - sms,
                     "screened_shots": int(stats[-1]["screened_shots"]),
                     "screened_at_t2": int(stats[-1]["screened2_shots"]),
                     "dense_shots": int(shots - stats[-1]["screened_shots"]),
-                    "what": "screen_ms: from the call's start to the end of k_screen12 "
-                            "(iterations 1 and 2 of the initial run, one wave per shot); "
-                            "dense_ms: the rest of the call, k_batched (the persistent decoder "
-                            "for the listed shots) launched beside the screen finishing the "
-                            "shots listed last, then the k_batched launch after the screen, "
-                            "which ends at once when nothing is left"},
+                    "what": "synchronous calls on one stream: screen_ms from the call's "
+                            "start to the end of k_screen12 (iterations 1 and 2 of the "
+                            "initial run, one wave per shot); dense_ms the rest of the call, "
+                            "k_batched (the persistent decoder) on the shots the screen lists"},
         "work_rate": {"edge_updates_per_s": iters * pr.nnz / (kms * 1e-3),
                       "bp_iterations_per_step": iters,
                       "what": "BP iterations x Tanner edges per second of kernel time; a work "

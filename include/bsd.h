@@ -98,7 +98,16 @@ typedef enum {
    * can send a negative message at t = 2, every other row's message is
    * bounded from below, and the columns whose bounded posterior is not
    * positive get exact messages.  Results are identical either way. */
-  BSD_FLAG_NO_SCREEN2 = 16
+  BSD_FLAG_NO_SCREEN2 = 16,
+  /* Batched mode with the screen: also launch the persistent decoder on a
+   * second stream beside the screen, where it takes the shots the screen
+   * hands on while the screen still runs, as compute units free up.  It is
+   * launched only while the stream's last synchronous call handed on under
+   * 2 % of its shots (beside a screen that hands on many it slows both), and
+   * not with BSD_FLAG_GRAPH.  The dense work then hides under the screen's
+   * last waves but slows them as much; calls pipelined on two streams fill
+   * that tail anyway.  Results are identical either way. */
+  BSD_FLAG_BESIDE = 32
 } bsd_flag;
 
 /* Work counters of one bsd_decode_ex call. */

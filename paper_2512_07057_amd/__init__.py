@@ -24,6 +24,7 @@ FLAG_DENSE_FIRST = 2
 FLAG_ALPHA_SCHEDULE = 4
 FLAG_NO_SCREEN = 8
 FLAG_NO_SCREEN2 = 16
+FLAG_BESIDE = 32
 _lib = None
 
 

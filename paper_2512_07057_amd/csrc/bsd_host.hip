@@ -71,8 +71,8 @@ uint32_t pow2_at_least(uint64_t x) {
 // slots), the screen's shot list, events, and the HIP graph of the last call
 // (BSD_FLAG_GRAPH).  Calls on one stream run in stream order, so they share
 // it; calls on different streams have their own and may run concurrently.
-// The decoder beside the screen runs while the screen hands on less than this
-// share of a call's shots.
+// With BSD_FLAG_BESIDE, the decoder beside the screen runs while the screen
+// hands on less than this share of a call's shots.
 constexpr double kBesideMaxListed = 0.02;
 
 struct Lane {
@@ -849,14 +849,15 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
     HIP_OR_FAIL(launch_batch_reset(a, s));
     HIP_OR_FAIL(hipEventRecord(l->ev0, s));
     if (screen) HIP_OR_FAIL(launch_screen(sa, sgrid, sgrid2, s));
-    // A dense decoder beside the screen, on a second stream: its workgroups
-    // start as the screen's leave the device and take the listed shots while
-    // the screen still runs.  The launch after the screen takes whatever it
-    // leaves (and ends at once when it left nothing).  It pays only when the
-    // screen hands on few shots (the dense work then hides under the
-    // screen's last waves); with more, running beside the screen slows both,
-    // so the share of the lane's last synchronous call decides.
-    const bool beside = screen && l->listed_frac < kBesideMaxListed;
+    // On request, a dense decoder beside the screen, on a second stream: its
+    // workgroups start as the screen's leave the device and take the listed
+    // shots while the screen still runs.  The launch after the screen takes
+    // whatever it leaves (and ends at once when it left nothing).  Only
+    // when the screen hands on few shots (the dense work then hides under
+    // the screen's last waves); with more, running beside the screen slows
+    // both, so the share of the lane's last synchronous call decides.
+    const bool beside =
+        screen && (p->flags & BSD_FLAG_BESIDE) && l->listed_frac < kBesideMaxListed;
     if (beside) {
       if (!l->side) {
         HIP_OR_FAIL(hipStreamCreateWithFlags(&l->side, hipStreamNonBlocking));
@@ -1677,7 +1678,6 @@ bsd_status launch_decoder(ServeQ& q, int index) {
     hipError_t he = launch_batched(q.args, q.grid, q.code->block, q.code->cpt, q.code->pw,
                                    q.code->lds, q.stream);
     if (he != hipSuccess) return fail(BSD_EDEVICE, "serving launch: %s", hipGetErrorString(he));
-    ++q.launches;
     const double t0 = now_us();
     bool begun = false;
     while (!(begun = __atomic_load_n(q.begun, __ATOMIC_ACQUIRE)) && now_us() - t0 < 250e3)
@@ -1690,6 +1690,7 @@ bsd_status launch_decoder(ServeQ& q, int index) {
       q.stream = ns;
       continue;
     }
+    ++q.launches;  // (a replaced launch is not counted)
     while (!__atomic_load_n(q.started, __ATOMIC_ACQUIRE)) {
       if (now_us() - t0 > 5e6)
         return fail(BSD_EDEVICE, "serving decoder %d (%d workgroups) did not have every "

@@ -75,10 +75,12 @@ def test_two_streams_concurrently(bsd):
         _same(_np(ob), ref_b, f"{wl} stream 2")
         if wl == "W1":  # ~40 ms of work per batch: the calls return well before it is done
             assert t_enqueue < 0.5 * t_all
-        # repeat on the same two streams: each keeps its own workspace
+        # repeat on the same two streams: each keeps its own workspace (the
+        # second time with a decoder beside each screen)
         for rep in range(2):
-            code.decode(b, prm, stream=s1, out=oa, sync=False)
-            code.decode(a, prm, stream=s2, out=ob, sync=False)
+            pr = prm if rep == 0 else _params(bsd, W.params, bsd.FLAG_BESIDE)
+            code.decode(b, pr, stream=s1, out=oa, sync=False)
+            code.decode(a, pr, stream=s2, out=ob, sync=False)
             code.sync(s1)
             code.sync(s2)
             _same(_np(oa), ref_b, f"{wl} swap {rep}")

@@ -67,13 +67,16 @@ def test_screen_equals_dense_first_iteration(bsd, wl, hot, shots):
     syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
     gc.log("screen", wl, hot, shots)
     outs = {}
-    for name, flags in (("screen", 0), ("screen1", bsd.FLAG_NO_SCREEN2),
+    # ("beside" right after "screen": the decoder beside the screen runs
+    # while the stream's last call handed on few shots)
+    for name, flags in (("screen", 0), ("beside", bsd.FLAG_BESIDE),
+                        ("screen1", bsd.FLAG_NO_SCREEN2),
                         ("no_screen", bsd.FLAG_NO_SCREEN), ("dense", bsd.FLAG_DENSE_FIRST)):
         r = code.decode(syn, _params(bsd, W.params, flags), latency=True)
         torch.cuda.synchronize()
         outs[name] = (_np(r), r["stats"], r["latency_ticks"].cpu().numpy())
         gc.log("  ", name, r["stats"])
-    for name in ("screen1", "no_screen", "dense"):
+    for name in ("beside", "screen1", "no_screen", "dense"):
         _check_same(outs["screen"][0], outs[name][0], name)
         assert outs["screen"][1]["deep_shots"] == outs[name][1]["deep_shots"], name
         if outs["screen"][1]["deep_shots"] == 0:
@@ -108,7 +111,7 @@ def test_screen_alpha_beyond_the_single_detector_flag(bsd, alpha):
         syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
         P = W.params
         outs = {}
-        for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN)):
+        for name, flags in (("screen", bsd.FLAG_BESIDE), ("no_screen", bsd.FLAG_NO_SCREEN)):
             prm = bsd.make_params(P.max_rounds, P.beam_width, P.initial_iters, P.iters_per_round,
                                   P.num_results, alpha, bsd.MODE_BATCHED, flags)
             r = code.decode(syn, prm)
@@ -123,15 +126,16 @@ def test_screen_alpha_beyond_the_single_detector_flag(bsd, alpha):
 def test_screen_tiny_batches(bsd):
     """Batches smaller than a workgroup's waves or than the dense decoder's
     grid, some shots handed on (W2 at 40x the priors): the screen, the
-    decoder launched beside it and the one after it end cleanly and agree
-    with the call without the screen."""
+    decoder launched beside it (when the stream's last call handed on few
+    shots) and the one after it end cleanly and agree with the call without
+    the screen."""
     W = workloads.WORKLOADS["W2"]
     code = _code(bsd, W.problem_key)
     for shots in (1, 7, 63, 300):
         syn = gc.samples("W2", shots, seed=31 + shots, hot=40 if shots < 300 else 0)["syndromes"]
         syn = torch.from_numpy(np.ascontiguousarray(syn)).cuda()
         outs = {}
-        for name, flags in (("screen", 0), ("no_screen", bsd.FLAG_NO_SCREEN)):
+        for name, flags in (("screen", bsd.FLAG_BESIDE), ("no_screen", bsd.FLAG_NO_SCREEN)):
             r = code.decode(syn, _params(bsd, W.params, flags))
             torch.cuda.synchronize()
             outs[name] = _np(r)
