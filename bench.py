@@ -237,10 +237,10 @@ def w1_leg(bsd, torch, steps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shots", type=int, default=100_000)
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=4,
                     help="streams the timed calls are spread over (each a workspace of its own)")
     ap.add_argument("--plain-shots", type=int, default=10_000)
     ap.add_argument("--legs", default=",".join(LEGS),

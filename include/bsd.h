@@ -165,8 +165,11 @@ bsd_status bsd_code_destroy(bsd_code code);
  * the device and reported by bsd_code_sync.  A handle may be used from
  * several streams at once (and from several host threads): each stream gets
  * a workspace of its own, allocated on its first batched call, for at most 8
- * streams per handle (BSD_EBUSY beyond).  Host buffers and the plain mode
- * are synchronous.
+ * streams per handle (BSD_EBUSY beyond).  Batches enqueued in turn on
+ * several streams overlap on the device: a call made while other streams'
+ * calls are still running gives the persistent decoder a share of its grid
+ * (results are identical).  Host buffers and the plain mode are
+ * synchronous.
  * Errors: BSD_EINVAL for bad parameters (and, when synchronous, syndrome
  * bytes outside {0,1}); BSD_ENOMEM when the workspace cannot be allocated;
  * BSD_EDEVICE. */

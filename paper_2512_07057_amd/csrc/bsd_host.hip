@@ -72,8 +72,11 @@ uint32_t pow2_at_least(uint64_t x) {
 // (BSD_FLAG_GRAPH).  Calls on one stream run in stream order, so they share
 // it; calls on different streams have their own and may run concurrently.
 // With BSD_FLAG_BESIDE, the decoder beside the screen runs while the screen
-// hands on less than this share of a call's shots.
+// hands on less than this share of a call's shots; below the same share the
+// decoder after the screen takes a share of the grid while other streams'
+// calls run.
 constexpr double kBesideMaxListed = 0.02;
+constexpr double kShareMaxListed = 0.02;
 
 struct Lane {
   hipStream_t stream = nullptr;
@@ -174,6 +177,19 @@ void drop_graph(Lane* l) {
   l->gexec = nullptr;
   l->graph = nullptr;
   l->gkey.clear();
+}
+
+// How many other streams' batched calls on this handle may still be running
+// (their lanes' end events not yet reached).  Skips the check (0) rather
+// than wait when another thread holds the lane list.
+int other_lanes_busy(bsd_code c, const Lane* self) {
+  std::unique_lock<std::mutex> lock(c->lanes_mu, std::try_to_lock);
+  if (!lock.owns_lock()) return 0;
+  int busy = 0;
+  for (const Lane* o : c->lanes)
+    if (o != self && o->done && hipEventQuery(o->done) == hipErrorNotReady) ++busy;
+  (void)hipGetLastError();  // (a query that is not ready is no error)
+  return busy;
 }
 
 // Wait until the lane's enqueued work has finished.
@@ -870,7 +886,16 @@ bsd_status decode_batched(bsd_code c, Lane* l, const bsd_params* p, const FiTab*
       HIP_OR_FAIL(hipEventRecord(l->ev_side, l->side));
     }
     HIP_OR_FAIL(hipEventRecord(l->evs, s));
-    HIP_OR_FAIL(launch_batched(a, c->grid, c->block, c->cpt, c->pw, c->lds, s));
+    // While other streams' calls run (calls pipelined on several streams)
+    // and the screen hands on few shots, the decoder after the screen takes
+    // an equal share of the grid: each workgroup holds a whole compute unit,
+    // mostly waiting on its few shots' iterations, and the other streams'
+    // screens get the rest.  On one stream the whole grid finishes those
+    // shots sooner.
+    const int others = screen && !beside && l->listed_frac < kShareMaxListed
+                           ? other_lanes_busy(c, l) : 0;
+    const int dgrid = std::max(1, c->grid / (1 + others));
+    HIP_OR_FAIL(launch_batched(a, dgrid, c->block, c->cpt, c->pw, c->lds, s));
     if (beside) HIP_OR_FAIL(hipStreamWaitEvent(s, l->ev_side, 0));
     HIP_OR_FAIL(hipEventRecord(l->ev1, s));
   }
