@@ -125,6 +125,35 @@ def test_host_threads_share_a_handle(bsd):
     assert not errors, errors[0]
 
 
+def test_pipelined_streams_share_the_grid(bsd):
+    """W2 batches enqueued in turn on four streams without waiting, as the
+    benchmark pipelines them: calls made while other streams' calls run give
+    the dense decoder a share of its grid.  Every output equals the same
+    batch decoded alone, synchronously."""
+    W = workloads.WORKLOADS["W2"]
+    code = bsd.Code.from_problem(gc.problem(W.problem_key))
+    prm = _params(bsd, W.params)
+    shots = 20_000
+    batches = [torch.from_numpy(gc.samples("W2", shots, seed=60 + i)["syndromes"]).cuda()
+               for i in range(4)]
+    refs = [_np(code.decode(x, prm)) for x in batches]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for st in streams:  # (a first synchronous call on each stream)
+        code.decode(batches[0], prm, stream=st)
+    torch.cuda.synchronize()
+    for rnd in range(2):
+        outs = [_empty(code, shots) for _ in range(8)]
+        for c in range(8):
+            code.decode(batches[(c + rnd) % 4], prm, stream=streams[c % 4], out=outs[c],
+                        sync=False)
+        for st in streams:
+            code.sync(st)
+        gc.log("pipelined round", rnd)
+        for c in range(8):
+            _same(_np(outs[c]), refs[(c + rnd) % 4], f"round {rnd} call {c}")
+    code.close()
+
+
 def test_async_errors_reported_by_sync(bsd):
     W = workloads.WORKLOADS["W0"]
     code = bsd.Code.from_problem(gc.problem(W.problem_key))
