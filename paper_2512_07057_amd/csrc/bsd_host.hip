@@ -1201,10 +1201,11 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
   c->maxdeg_col = maxdeg_col;
   // A workgroup of 1024 lanes holds up to 9 columns per lane in registers;
   // beyond that 512 lanes get twice the registers.  Small graphs get 512-lane
-  // workgroups, two per CU: with thousands of single-wave workgroups, the
+  // workgroups, one per CU: with thousands of single-wave workgroups, the
   // idle ones' polling of the queue counters slowed the busy ones' atomics
-  // (W0, W1 and the XYZ workload ran 1.3 to 4.7 times slower).  BSD_BLOCK
-  // overrides the choice; bsd_code_autotune measures.
+  // (W0, W1 and the XYZ workload ran 1.3 to 4.7 times slower), and two per
+  // CU ran 7 to 30 % slower than one (fewer than one per CU, slower still).
+  // BSD_BLOCK overrides the choice; bsd_code_autotune measures.
   int block;
   if (c->lds > 64 * 1024) {
     block = supported_cpt((n + 1023) / 1024) <= 9 ? 1024 : 512;
@@ -1217,7 +1218,7 @@ bsd_status bsd_code_create(int32_t m, int32_t n, int32_t k, const int32_t* h_col
     if (b >= 64 && b <= 1024 && (b & (b - 1)) == 0) block = b;
   }
   {
-    bsd_status gs = set_geometry(c, block, 0);
+    bsd_status gs = set_geometry(c, block, c->lds > 64 * 1024 ? 0 : 1);
     if (gs != BSD_OK) {
       std::string msg = g_err;
       bsd_code_destroy(c);
