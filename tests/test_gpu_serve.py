@@ -128,9 +128,9 @@ def test_decoders_restart_after_idle(bsd, setup):
             gc.log("cycle", cycle, info)
             assert not any(x["running"] for x in info), info
             # one launch per cycle after the first (a decoder may also have
-            # idled out once before the first requests, while the server
-            # started the other)
+            # idled out before the first requests, while the server started
+            # the other)
             if base is None:
                 base = [x["launches"] for x in info]
-                assert all(1 <= b <= 2 for b in base), info
+                assert all(b >= 1 for b in base), info
             assert all(x["launches"] == b + cycle for x, b in zip(info, base)), (base, info)
